@@ -1,0 +1,159 @@
+/*
+ * fdd.h -- C ABI of the MI355X (gfx950) Fourier-domain dedispersion library.
+ *
+ * Method: Bassa et al., "Fourier-domain dedispersion" (arXiv:2110.03482), Sec. 2.2 and
+ * Sec. 3.  For every channel c and trial DM, the dispersion delay (Eq. 1)
+ *     tau[dm, c] = DM_dm * k_DM * (nu_c^-2 - nu_ref^-2) / t_samp      (samples)
+ * is applied in the Fourier domain of time:
+ *     X[c, k, f] = sum_t x[c, kS + t] exp(-2 pi i f t / L)             (Eq. 3, per chunk k)
+ *     Y[dm, k, f] = sum_c X[c, k, f] exp(+2 pi i f tau[dm, c] / L)     (Eqs. 4 and 7)
+ *     y[dm, kS + t] = (1/L) IDFT_L(Y[dm, k, .])[t],  t < S             (Eq. 6, wrap discarded)
+ * or, without the inverse transform, power spectra |Y[dm, 0, f]|^2 (Sec. 5).
+ *
+ * Conventions fixed by this library (readings of the paper):
+ *  - k_DM = FDD_K_DM.  nu_ref must be >= every channel frequency, so tau >= 0.
+ *  - Output sample t of a DM sums input samples t + tau[dm, c] (lower frequencies arrive
+ *    later and are advanced); hence the phasor sign +2 pi i above.
+ *  - Delays are formed in float64 as kappa_c = (k_DM * (1/(nu_c*nu_c) - 1/(nu_ref*nu_ref)))
+ *    / t_samp and tau = DM * kappa_c.  FDD_DELAY_ROUND uses d = floor(tau + 1/2) (Sec. 2.1,
+ *    nearest sample), for which the result equals time-domain shift-and-sum (Eq. 2).
+ *  - Chunked mode is overlap-save: chunk k covers input samples [kS, kS + L), zero beyond
+ *    n_samp, and keeps its first S = L - D outputs; D >= ceil(max tau) (Sec. 2.2).
+ *    Single-chunk mode zero-pads n_samp to L and is circular over L.
+ *  - The inverse drops Im of bins 0 and L/2 and scales by 1/L.  Power spectra keep bins
+ *    0 .. L/2-1 and are not normalised.
+ *
+ * Memory and streams: every pointer named d_* is device memory owned by the caller.  All
+ * device work is enqueued on the given stream (a hipStream_t; NULL = the null stream) and
+ * nothing synchronises the host, except where stated.  A plan owns one workspace, so one
+ * plan must not run concurrently on two streams; distinct plans are independent.
+ *
+ * Errors: every call returns an fdd_status.  Nothing throws across the ABI.  The text of the
+ * most recent failure on the calling thread is available from fdd_last_error().
+ */
+#ifndef FDD_H
+#define FDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Dispersion constant, MHz^2 pc^-1 cm^3 s (Eq. 1). */
+#define FDD_K_DM 4.148808e3
+
+typedef enum {
+  FDD_OK = 0,
+  FDD_E_INVALID = 1,      /* bad argument or descriptor field */
+  FDD_E_OVERLAP = 2,      /* overlap shorter than the maximum delay, or not shorter than L */
+  FDD_E_UNSUPPORTED = 3,  /* valid request this build does not implement */
+  FDD_E_NOMEM = 4,        /* device allocation failed, or size overflow */
+  FDD_E_DEVICE = 5,       /* a HIP call failed (detail in fdd_last_error) */
+  FDD_E_WORKSPACE = 6     /* no workspace attached, or the attached one is too small */
+} fdd_status;
+
+typedef enum {
+  FDD_IN_U8_TIME_MAJOR = 0,  /* uint8 [n_samp][n_chan] (packed 8-bit filterbank, Sec. 3) */
+  FDD_IN_F32_CHAN_MAJOR = 1  /* float32 [n_chan][n_samp] */
+} fdd_input_kind;
+
+typedef enum {
+  FDD_FP32 = 0,        /* phasor sum in float32 */
+  FDD_FP16_SPLIT = 1,  /* hi/lo float16 phasors and data on MFMA, float32 accumulation (Sec. 5 outlook) */
+  FDD_BF16_SPLIT = 2   /* hi/lo bfloat16 phasors and data on MFMA, float32 accumulation */
+} fdd_precision;
+
+typedef enum {
+  FDD_DELAY_EXACT = 0, /* fractional delays, phase frac(f tau / L) (Eq. 4) */
+  FDD_DELAY_ROUND = 1  /* delays rounded to the nearest sample (Eq. 2 equivalent) */
+} fdd_delay_mode;
+
+/* Plan flags. */
+#define FDD_PLAN_DRY_RUN 1u             /* validate and size only; no device calls at all */
+#define FDD_PLAN_EXTERNAL_WORKSPACE 2u  /* caller attaches the workspace with fdd_set_workspace */
+
+typedef struct {
+  int32_t n_chan;               /* channels, >= 1 */
+  const double* chan_freq_mhz;  /* host array [n_chan], any order, 0 < nu_c <= ref_freq_mhz; copied */
+  double ref_freq_mhz;          /* nu_ref of Eq. 1 (the upper band edge) */
+  double tsamp_s;               /* sampling time, > 0 */
+  int32_t n_dm;                 /* trial DMs, >= 1 */
+  const double* dm;             /* host array [n_dm], finite, >= 0 (pc cm^-3); copied */
+  int64_t n_samp;               /* time samples per channel, >= 1 */
+  int64_t chunk_len;            /* FFT length L: power of two, 2^6 .. 2^16 */
+  int64_t overlap;              /* D = L - S; <= 0 picks ceil(max tau); ignored if single_chunk */
+  int32_t single_chunk;         /* 1: one circular transform of length L >= n_samp */
+  int32_t input;                /* fdd_input_kind */
+  int32_t precision;            /* fdd_precision */
+  int32_t delay_mode;           /* fdd_delay_mode */
+  uint32_t flags;               /* FDD_PLAN_* */
+} fdd_plan_desc;
+
+typedef struct {
+  int64_t chunk_len;        /* L */
+  int64_t stride;           /* S = samples kept per chunk (L in single-chunk mode) */
+  int64_t overlap;          /* D (0 in single-chunk mode) */
+  int64_t n_chunks;         /* ceil(n_samp / S) */
+  int64_t n_bins;           /* L/2 + 1 Fourier bins per chunk */
+  int64_t bins_padded;      /* row pitch (in bins) of the Fourier-domain buffers */
+  double max_delay;         /* max over (dm, c) of tau, samples */
+  int64_t n_valid;          /* samples not touched by the end-of-series discard: n_samp - ceil(max tau) */
+  size_t workspace_bytes;   /* device bytes a workspace for this plan must hold */
+} fdd_plan_geometry;
+
+typedef struct fdd_plan_s* fdd_plan_t;
+
+/* Build a plan: validate the descriptor, copy the host arrays, compute the per-channel delay
+ * per unit DM in float64 and the chunk geometry.  Without FDD_PLAN_EXTERNAL_WORKSPACE or
+ * FDD_PLAN_DRY_RUN it allocates its workspace on the current device.
+ * Errors: FDD_E_INVALID, FDD_E_OVERLAP, FDD_E_UNSUPPORTED, FDD_E_NOMEM, FDD_E_DEVICE. */
+fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out);
+
+/* Geometry and workspace size of a plan (host only). */
+fdd_status fdd_plan_info(fdd_plan_t plan, fdd_plan_geometry* out);
+
+/* Attach caller-owned device memory of at least workspace_bytes (256-byte aligned) as the
+ * plan's workspace.  Synchronously uploads the plan's small tables into it.  The caller keeps
+ * ownership and must keep it alive while the plan is used. */
+fdd_status fdd_set_workspace(fdd_plan_t plan, void* d_workspace, size_t bytes);
+
+/* Dedisperse: d_in is described by the plan's input kind; d_out is float32 [n_dm][n_samp]
+ * (DM-major, Sec. 3).  Enqueued on `stream`; does not synchronise.
+ * Errors: FDD_E_INVALID (null pointers, dry-run plan), FDD_E_WORKSPACE, FDD_E_DEVICE. */
+fdd_status fdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
+
+/* Power spectra without the inverse transform (Sec. 5): d_out is float32 [n_dm][L/2],
+ * |Y[dm, f]|^2 for f = 0 .. L/2-1.  Single-chunk plans only (FDD_E_UNSUPPORTED otherwise). */
+fdd_status fdd_power_spectrum(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
+
+/* Release a plan and the workspace it allocated itself (never a caller-owned one). */
+fdd_status fdd_destroy(fdd_plan_t plan);
+
+/* Stage timing.  With profiling enabled, fdd_execute / fdd_power_spectrum record HIP events
+ * on their stream around each stage; fdd_profile_read waits for the last call's events and
+ * returns milliseconds for [0] transpose/unpack, [1] forward FFT, [2] phasor sum,
+ * [3] inverse FFT (0 for a stage that did not run). */
+fdd_status fdd_profile_enable(fdd_plan_t plan, int32_t enable);
+fdd_status fdd_profile_read(fdd_plan_t plan, float ms[4]);
+
+/* Host helpers. */
+/* tau (samples) of every channel at one DM, Eq. 1, exactly as plans compute it. */
+fdd_status fdd_dispersion_delays(int32_t n_chan, const double* chan_freq_mhz, double ref_freq_mhz,
+                                 double tsamp_s, double dm, double* tau_out);
+/* The plan's float64 delay table tau[n_dm][n_chan] (host copy). */
+fdd_status fdd_plan_delays(fdd_plan_t plan, double* tau_out);
+/* Name of the phasor-sum kernel family a plan selected ("valu", "mfma_f32", ...). */
+const char* fdd_plan_kernel(fdd_plan_t plan);
+
+const char* fdd_status_string(fdd_status s);
+const char* fdd_last_error(void);
+/* Library version string. */
+const char* fdd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDD_H */

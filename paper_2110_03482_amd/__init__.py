@@ -1,0 +1,323 @@
+"""Python binding of the gfx950 Fourier-domain dedispersion library (libfdd.so).
+
+Argument marshalling only: every stage of the path runs in the library's HIP kernels.  PyTorch
+provides device memory (inputs, outputs, the plan workspace) and the HIP stream.  There is no
+CPU fallback: if the library is missing or no GPU is present, calls fail loudly.
+
+Low-level functions carry the C ABI names (fdd_plan, fdd_execute, fdd_power_spectrum, ...);
+`Plan` wraps them for tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "FDD_OK", "FDD_IN_U8_TIME_MAJOR", "FDD_IN_F32_CHAN_MAJOR", "FDD_FP32", "FDD_FP16_SPLIT",
+    "FDD_BF16_SPLIT", "FDD_DELAY_EXACT", "FDD_DELAY_ROUND", "FDD_PLAN_DRY_RUN",
+    "FDD_PLAN_EXTERNAL_WORKSPACE", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
+    "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
+    "fdd_power_spectrum", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
+    "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_kernel", "fdd_status_string",
+    "fdd_last_error", "fdd_version", "Plan",
+]
+
+FDD_OK = 0
+FDD_IN_U8_TIME_MAJOR, FDD_IN_F32_CHAN_MAJOR = 0, 1
+FDD_FP32, FDD_FP16_SPLIT, FDD_BF16_SPLIT = 0, 1, 2
+FDD_DELAY_EXACT, FDD_DELAY_ROUND = 0, 1
+FDD_PLAN_DRY_RUN, FDD_PLAN_EXTERNAL_WORKSPACE = 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "lib", "libfdd.so")
+
+
+class FddError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {fdd_status_string(status)} ({status}): {fdd_last_error()}")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_chan", ctypes.c_int32),
+        ("chan_freq_mhz", ctypes.POINTER(ctypes.c_double)),
+        ("ref_freq_mhz", ctypes.c_double),
+        ("tsamp_s", ctypes.c_double),
+        ("n_dm", ctypes.c_int32),
+        ("dm", ctypes.POINTER(ctypes.c_double)),
+        ("n_samp", ctypes.c_int64),
+        ("chunk_len", ctypes.c_int64),
+        ("overlap", ctypes.c_int64),
+        ("single_chunk", ctypes.c_int32),
+        ("input", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("delay_mode", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class PlanGeometry(ctypes.Structure):
+    _fields_ = [
+        ("chunk_len", ctypes.c_int64),
+        ("stride", ctypes.c_int64),
+        ("overlap", ctypes.c_int64),
+        ("n_chunks", ctypes.c_int64),
+        ("n_bins", ctypes.c_int64),
+        ("bins_padded", ctypes.c_int64),
+        ("max_delay", ctypes.c_double),
+        ("n_valid", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+_SIGNATURES = {
+    "fdd_plan": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "fdd_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanGeometry)]),
+    "fdd_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "fdd_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdd_power_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdd_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fdd_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "fdd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "fdd_dispersion_delays": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "fdd_plan_delays": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "fdd_plan_kernel": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "fdd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fdd_last_error": (ctypes.c_char_p, []),
+    "fdd_version": (ctypes.c_char_p, []),
+}
+
+
+def library() -> ctypes.CDLL:
+    """Load libfdd.so (built by paper_2110_03482_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError(f"{library_path} is missing: build it with `python -m paper_2110_03482_amd.build`")
+        lib = ctypes.CDLL(library_path)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols() -> list:
+    return sorted(_SIGNATURES)
+
+
+def _check(status: int, where: str) -> None:
+    if status != FDD_OK:
+        raise FddError(status, where)
+
+
+def _dptr(a) -> ctypes.POINTER(ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ----------------------------------------------------------------------------- C ABI mirrors
+
+def fdd_status_string(status: int) -> str:
+    return library().fdd_status_string(int(status)).decode()
+
+
+def fdd_last_error() -> str:
+    return library().fdd_last_error().decode()
+
+
+def fdd_version() -> str:
+    return library().fdd_version().decode()
+
+
+def fdd_plan(desc: PlanDesc) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(library().fdd_plan(ctypes.byref(desc), ctypes.byref(h)), "fdd_plan")
+    return h
+
+
+def fdd_plan_info(plan) -> PlanGeometry:
+    g = PlanGeometry()
+    _check(library().fdd_plan_info(plan, ctypes.byref(g)), "fdd_plan_info")
+    return g
+
+
+def fdd_set_workspace(plan, ptr: int, nbytes: int) -> None:
+    _check(library().fdd_set_workspace(plan, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)), "fdd_set_workspace")
+
+
+def fdd_execute(plan, d_in: int, d_out: int, stream: int = 0) -> None:
+    _check(library().fdd_execute(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out), ctypes.c_void_p(stream)),
+           "fdd_execute")
+
+
+def fdd_power_spectrum(plan, d_in: int, d_out: int, stream: int = 0) -> None:
+    _check(library().fdd_power_spectrum(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
+                                        ctypes.c_void_p(stream)), "fdd_power_spectrum")
+
+
+def fdd_destroy(plan) -> None:
+    _check(library().fdd_destroy(plan), "fdd_destroy")
+
+
+def fdd_profile_enable(plan, enable: bool) -> None:
+    _check(library().fdd_profile_enable(plan, int(bool(enable))), "fdd_profile_enable")
+
+
+def fdd_profile_read(plan) -> list:
+    ms = (ctypes.c_float * 4)()
+    _check(library().fdd_profile_read(plan, ms), "fdd_profile_read")
+    return [float(v) for v in ms]
+
+
+def fdd_dispersion_delays(freqs_mhz: Sequence[float], ref_freq_mhz: float, tsamp_s: float, dm: float) -> np.ndarray:
+    f = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
+    out = np.empty_like(f)
+    _check(library().fdd_dispersion_delays(int(f.size), _dptr(f), float(ref_freq_mhz), float(tsamp_s), float(dm),
+                                           _dptr(out)), "fdd_dispersion_delays")
+    return out
+
+
+def fdd_plan_delays(plan, n_dm: int, n_chan: int) -> np.ndarray:
+    out = np.empty((n_dm, n_chan), dtype=np.float64)
+    _check(library().fdd_plan_delays(plan, _dptr(out)), "fdd_plan_delays")
+    return out
+
+
+def fdd_plan_kernel(plan) -> str:
+    return library().fdd_plan_kernel(plan).decode()
+
+
+# ----------------------------------------------------------------------------- tensor wrapper
+
+_PRECISIONS = {"fp32": FDD_FP32, "fp16_split": FDD_FP16_SPLIT, "bf16_split": FDD_BF16_SPLIT}
+_MODES = {"exact": FDD_DELAY_EXACT, "round": FDD_DELAY_ROUND}
+_INPUTS = {"u8": FDD_IN_U8_TIME_MAJOR, "f32": FDD_IN_F32_CHAN_MAJOR}
+
+
+class Plan:
+    """A dedispersion plan with a workspace allocated from torch on `device`.
+
+    Input tensors: uint8 [n_samp][n_chan] (input="u8") or float32 [n_chan][n_samp] ("f32").
+    """
+
+    def __init__(self, freqs_mhz, ref_freq_mhz: float, tsamp_s: float, dms, n_samp: int, chunk_len: int,
+                 overlap: int = 0, single_chunk: bool = False, input: str = "f32", precision: str = "fp32",
+                 mode: str = "exact", device=None, dry_run: bool = False):
+        self._freqs = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
+        self._dms = np.ascontiguousarray(dms, dtype=np.float64)
+        self.n_chan = int(self._freqs.size)
+        self.n_dm = int(self._dms.size)
+        self.n_samp = int(n_samp)
+        self.input = input
+        self.single_chunk = bool(single_chunk)
+        d = PlanDesc()
+        d.n_chan = self.n_chan
+        d.chan_freq_mhz = _dptr(self._freqs)
+        d.ref_freq_mhz = float(ref_freq_mhz)
+        d.tsamp_s = float(tsamp_s)
+        d.n_dm = self.n_dm
+        d.dm = _dptr(self._dms)
+        d.n_samp = self.n_samp
+        d.chunk_len = int(chunk_len)
+        d.overlap = int(overlap)
+        d.single_chunk = int(self.single_chunk)
+        d.input = _INPUTS[input]
+        d.precision = _PRECISIONS[precision]
+        d.delay_mode = _MODES[mode]
+        d.flags = FDD_PLAN_DRY_RUN if dry_run else FDD_PLAN_EXTERNAL_WORKSPACE
+        self._handle = fdd_plan(d)
+        self.geometry = fdd_plan_info(self._handle)
+        self.kernel = fdd_plan_kernel(self._handle)
+        self.workspace = None
+        self.device = None
+        if not dry_run:
+            import torch
+            if not torch.cuda.is_available():
+                fdd_destroy(self._handle)
+                self._handle = None
+                raise RuntimeError("no GPU visible: the FDD library has no CPU path")
+            self.device = torch.device("cuda") if device is None else torch.device(device)
+            self.workspace = torch.empty(int(self.geometry.workspace_bytes), dtype=torch.uint8, device=self.device)
+            fdd_set_workspace(self._handle, self.workspace.data_ptr(), self.workspace.numel())
+
+    # -- helpers
+    @property
+    def handle(self):
+        return self._handle
+
+    def delays(self) -> np.ndarray:
+        return fdd_plan_delays(self._handle, self.n_dm, self.n_chan)
+
+    def _check_input(self, x):
+        import torch
+        if self.input == "u8":
+            want = (torch.uint8, (self.n_samp, self.n_chan))
+        else:
+            want = (torch.float32, (self.n_chan, self.n_samp))
+        if x.dtype != want[0] or tuple(x.shape) != want[1] or not x.is_contiguous() or x.device != self.workspace.device:
+            raise ValueError(f"input must be a contiguous {want[0]} tensor of shape {want[1]} on {self.device}")
+
+    @staticmethod
+    def _stream(stream) -> int:
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        return int(s.cuda_stream)
+
+    def execute(self, x, out=None, stream=None):
+        """Dedispersed series float32 [n_dm][n_samp]."""
+        import torch
+        self._check_input(x)
+        if out is None:
+            out = torch.empty((self.n_dm, self.n_samp), dtype=torch.float32, device=self.device)
+        elif out.dtype != torch.float32 or tuple(out.shape) != (self.n_dm, self.n_samp) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor [n_dm][n_samp]")
+        fdd_execute(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
+        return out
+
+    def power_spectrum(self, x, out=None, stream=None):
+        """Power spectra float32 [n_dm][L/2] (single-chunk plans)."""
+        import torch
+        self._check_input(x)
+        nb = int(self.geometry.chunk_len) // 2
+        if out is None:
+            out = torch.empty((self.n_dm, nb), dtype=torch.float32, device=self.device)
+        elif out.dtype != torch.float32 or tuple(out.shape) != (self.n_dm, nb) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor [n_dm][L/2]")
+        fdd_power_spectrum(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
+        return out
+
+    def profile(self, enable: bool = True) -> None:
+        fdd_profile_enable(self._handle, enable)
+
+    def stage_ms(self) -> list:
+        """[transpose, forward FFT, phasor sum, inverse FFT] of the last call, in ms."""
+        return fdd_profile_read(self._handle)
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None:
+            fdd_destroy(self._handle)
+            self._handle = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,120 @@
+// Stage sequencing of fdd_execute / fdd_power_spectrum (Algorithm 1 without host copies:
+// inputs and outputs are device resident, so there is nothing to overlap with PCIe).
+#include "fdd_internal.h"
+
+using namespace fdd;
+
+namespace {
+
+fdd_status check_ready(fdd_plan_t p, const void* in, const float* out) {
+  if (p == nullptr) return fail(FDD_E_INVALID, "null plan");
+  if (p->dry_run) return fail(FDD_E_INVALID, "a dry-run plan cannot execute");
+  if (in == nullptr || out == nullptr) return fail(FDD_E_INVALID, "null input or output");
+  if (p->d_ws == nullptr) return fail(FDD_E_WORKSPACE, "no workspace attached");
+  return FDD_OK;
+}
+
+void mark(fdd_plan_t p, int i, hipStream_t st) {
+  if (!p->profile) return;
+  p->ev_recorded[i] = hipEventRecord(p->ev[i], st) == hipSuccess;
+}
+
+fdd_status forward(fdd_plan_t p, const void* in, hipStream_t st) {
+  const fdd_plan_desc& d = p->desc;
+  FftArgs f;
+  if (d.input == FDD_IN_U8_TIME_MAJOR) {
+    uint8_t* xt = p->d_ws + p->ws.xt;
+    hipError_t e = launch_transpose_u8((const uint8_t*)in, xt, d.n_samp, d.n_chan, st);
+    if (e != hipSuccess) return hip_fail(e, "transpose launch");
+    f.in_u8 = xt;
+  } else {
+    f.in_f32 = (const float*)in;
+  }
+  mark(p, 1, st);
+  f.X = (float2*)(p->d_ws + p->ws.X);
+  f.twL = (const float2*)(p->d_ws + p->ws.tw);
+  f.n_samp = d.n_samp;
+  f.stride = p->S;
+  f.pitch = p->pitch;
+  f.n_chunks = (int)p->n_chunks;
+  f.n_rows = d.n_chan;
+  hipError_t e = launch_r2c(p->log_len - 1, f, st);
+  if (e != hipSuccess) return hip_fail(e, "forward FFT launch");
+  mark(p, 2, st);
+  return FDD_OK;
+}
+
+PhasorArgs phasor_args(fdd_plan_t p) {
+  PhasorArgs a;
+  a.X = (const float2*)(p->d_ws + p->ws.X);
+  a.dms = (const double*)(p->d_ws + p->ws.dms);
+  a.kappa = (const double*)(p->d_ws + p->ws.kappa);
+  a.col_scale = (const float*)(p->d_ws + p->ws.scale);
+  a.n_dm = p->desc.n_dm;
+  a.n_chan = p->desc.n_chan;
+  a.n_chunks = (int)p->n_chunks;
+  a.pitch = p->pitch;
+  a.n_bins = (int)p->n_bins;
+  a.n_pow_bins = (int)(p->L / 2);
+  a.log_len = p->log_len;
+  a.mode = p->desc.delay_mode;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
+  fdd_status s = check_ready(p, in, out);
+  if (s != FDD_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  mark(p, 0, st);
+  s = forward(p, in, st);
+  if (s != FDD_OK) return s;
+  PhasorArgs a = phasor_args(p);
+  a.Yr = (float*)(p->d_ws + p->ws.Yr);
+  a.Yi = (float*)(p->d_ws + p->ws.Yi);
+  hipError_t e = p->kernel == "mfma_f32" ? launch_phasor_mfma_f32(a, st) : launch_phasor_valu(a, st);
+  if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+  mark(p, 3, st);
+  FftArgs f;
+  f.Yr = a.Yr;
+  f.Yi = a.Yi;
+  f.out = out;
+  f.twL = (const float2*)(p->d_ws + p->ws.tw);
+  f.n_samp = p->desc.n_samp;
+  f.stride = p->S;
+  f.keep = p->desc.single_chunk ? p->desc.n_samp : p->S;
+  f.pitch = p->pitch;
+  f.n_chunks = (int)p->n_chunks;
+  f.n_rows = p->desc.n_dm;
+  f.add_full = p->desc.input == FDD_IN_U8_TIME_MAJOR ? 128.0f * (float)p->desc.n_chan : 0.0f;
+  e = launch_c2r(p->log_len - 1, f, st);
+  if (e != hipSuccess) return hip_fail(e, "inverse FFT launch");
+  mark(p, 4, st);
+  return FDD_OK;
+}
+
+fdd_status fdd_power_spectrum(fdd_plan_t p, const void* in, float* out, void* stream) {
+  fdd_status s = check_ready(p, in, out);
+  if (s != FDD_OK) return s;
+  if (!p->desc.single_chunk) return fail(FDD_E_UNSUPPORTED, "power spectra need a single-chunk plan");
+  hipStream_t st = (hipStream_t)stream;
+  mark(p, 0, st);
+  s = forward(p, in, st);
+  if (s != FDD_OK) return s;
+  PhasorArgs a = phasor_args(p);
+  a.P = out;
+  // the forward transform removed the 8-bit zero point from a chunk filling the whole
+  // transform; the removed offset sits in bin 0 only, with phasor 1
+  if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
+    a.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
+  hipError_t e = launch_phasor_valu(a, st);
+  if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+  mark(p, 3, st);
+  mark(p, 4, st);
+  return FDD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+// Workgroup-resident complex FFT for gfx950 (Stockham autosort, radix up to 32).
+//
+// A transform of N = 2^LOGN complex points is held in registers by T = N / E threads,
+// E = 2^LOGE points each: thread t owns points t + T*q, q < E.  Every pass of radix R
+// (R <= E) performs E/R butterflies per thread; butterfly j = t + T*b reads points
+// j + r*N/R, which are exactly the thread's own points b + r*E/R, so loads never cross
+// threads.  Only the scatter of a pass's outputs to their autosort positions
+//     (j / Ns) * Ns * R + (j mod Ns) + r * Ns
+// needs LDS.  After the last pass the outputs land back in the owner's registers in natural
+// order, so the last pass needs no exchange.  The exchange moves real and imaginary parts in
+// two rounds through an N-float buffer so that a 2^15-point transform fits in LDS.
+//
+// The radix-R butterfly is an in-register radix-2 decimation-in-frequency network whose
+// twiddles are compile-time constants; its bit-reversed result is renamed back at no cost.
+// Pass twiddles are evaluated in registers from their exact fixed-point angle (sincos_turn),
+// which keeps long-latency loads out of the passes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+
+namespace fdd {
+
+// exp(-2 pi i p / 2^32) (forward) or exp(+2 pi i p / 2^32) (INV).
+template <bool INV>
+__device__ __forceinline__ float2 turn_phasor(uint32_t p) {
+  float s, c;
+  sincos_turn(p, &s, &c);
+  return make_float2(c, INV ? s : -s);
+}
+
+// ----------------------------------------------------------------------------- constexpr trig
+// Taylor series evaluated in double at compile time, argument reduced to [-pi, pi].
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double cx_reduce(double x) {
+  while (x > kPi) x -= 2.0 * kPi;
+  while (x < -kPi) x += 2.0 * kPi;
+  return x;
+}
+constexpr double cx_sin(double x) {
+  x = cx_reduce(x);
+  double term = x, sum = x;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos(double x) {
+  x = cx_reduce(x);
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+// exp(sign * 2 pi i m / R) as float constants.
+template <int R, bool INV>
+struct RootTable {
+  float c[R];
+  float s[R];
+  constexpr RootTable() : c(), s() {
+    for (int m = 0; m < R; ++m) {
+      const double a = (INV ? 2.0 : -2.0) * kPi * m / R;
+      c[m] = (float)cx_cos(a);
+      s[m] = (float)cx_sin(a);
+    }
+  }
+};
+
+__device__ __forceinline__ float2 f2add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 f2sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// d * exp(sign * 2 pi i m / R) with the trivial factors 1 and -/+i special-cased.
+template <int R, bool INV>
+__device__ __forceinline__ float2 twiddle_const(float2 d, int m) {
+  constexpr RootTable<R, INV> tab{};
+  if (m == 0) return d;
+  if (4 * m == R) return INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+  const float c = tab.c[m], s = tab.s[m];
+  return make_float2(fmaf(d.x, c, -d.y * s), fmaf(d.x, s, d.y * c));
+}
+
+constexpr int cx_bitrev(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r = (r << 1) | ((v >> i) & 1);
+  return r;
+}
+constexpr int cx_log2(int v) { return v <= 1 ? 0 : 1 + cx_log2(v >> 1); }
+
+// In-place R-point DFT of a[0..R), sign -1 (forward) or +1 (INV), natural-order output.
+template <int R, bool INV>
+__device__ __forceinline__ void dft_reg(float2* a) {
+#pragma unroll
+  for (int half = R / 2; half >= 1; half >>= 1) {
+#pragma unroll
+    for (int s = 0; s < R; s += 2 * half) {
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const float2 u = a[s + i], w = a[s + i + half];
+        a[s + i] = f2add(u, w);
+        a[s + i + half] = twiddle_const<R, INV>(f2sub(u, w), i * (R / (2 * half)));
+      }
+    }
+  }
+  float2 t[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) t[k] = a[cx_bitrev(k, cx_log2(R))];
+#pragma unroll
+  for (int k = 0; k < R; ++k) a[k] = t[k];
+}
+
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+
+template <int LOGN>
+struct LdsSize {
+  static constexpr int floats = (1 << LOGN) + ((1 << LOGN) >> 5);
+};
+
+template <int LOGN, int LOGE, bool INV, int LOGRMAX = 4>
+struct BlockFft {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int E = 1 << LOGE;
+  static constexpr int T = N / E;
+
+  // One Stockham pass over sub-transform size Ns = 2^LOGNS; recursion runs the rest.
+  template <int LOGNS>
+  __device__ __forceinline__ static void pass(float2 (&v)[E], float* lds) {
+    if constexpr (LOGNS < LOGN) {
+      constexpr int LOGRC = LOGE < LOGRMAX ? LOGE : LOGRMAX;    // radix cap
+      constexpr int LOGR = (LOGRC < LOGN - LOGNS) ? LOGRC : (LOGN - LOGNS);
+      constexpr int R = 1 << LOGR;
+      constexpr int NB = E / R;          // butterflies per thread
+      constexpr int Ns = 1 << LOGNS;
+      constexpr bool last = (LOGNS + LOGR == LOGN);
+      const int t = threadIdx.x;
+      // butterflies in place: the outputs of butterfly b overwrite its inputs, slot b + r*NB
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = t + T * b;
+        const int k = j & (Ns - 1);
+        float2 a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = v[b + r * NB];
+        if constexpr (Ns > 1) {
+          // a[r] *= w^r with w = exp(-/+ 2 pi i k / (Ns R)).  The angle of w^r is r k / (Ns R)
+          // of a turn, an exact 32-bit fixed-point fraction.  For R > 8, w^r = w^(8u) w^v
+          // (r = 8u + v): R/8 + 6 evaluations instead of R - 1, one extra rounding for some.
+          constexpr int SH = 32 - LOGNS - LOGR;
+          constexpr int G = R > 8 ? 8 : R;
+          float2 lo[G];
+#pragma unroll
+          for (int vv = 1; vv < G; ++vv) lo[vv] = turn_phasor<INV>((uint32_t)(vv * k) << SH);
+#pragma unroll
+          for (int u = 0; u < R / G; ++u) {
+            float2 hi = make_float2(1.0f, 0.0f);
+            if (u > 0) hi = turn_phasor<INV>((uint32_t)(u * G * k) << SH);
+#pragma unroll
+            for (int vv = 0; vv < G; ++vv) {
+              const int r = u * G + vv;
+              if (r == 0) continue;
+              float2 w = vv == 0 ? hi : (u == 0 ? lo[vv] : make_float2(fmaf(hi.x, lo[vv].x, -hi.y * lo[vv].y),
+                                                                      fmaf(hi.x, lo[vv].y, hi.y * lo[vv].x)));
+              a[r] = make_float2(fmaf(a[r].x, w.x, -a[r].y * w.y), fmaf(a[r].x, w.y, a[r].y * w.x));
+            }
+          }
+        }
+        dft_reg<R, INV>(a);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b + r * NB] = a[r];
+      }
+      // After the last pass the outputs already sit on the owner's points in natural order.
+      if constexpr (!last) {
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int j = t + T * b;
+            const int k = j & (Ns - 1);
+            const int base = ((j >> LOGNS) << (LOGNS + LOGR)) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * Ns)] = part ? v[b + r * NB].y : v[b + r * NB].x;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < E; ++q) {
+            const float val = lds[lds_pad(t + T * q)];
+            if (part) v[q].y = val; else v[q].x = val;
+          }
+          __syncthreads();
+        }
+        pass<LOGNS + LOGR>(v, lds);
+      }
+    }
+  }
+
+  __device__ __forceinline__ static void run(float2 (&v)[E], float* lds) {
+    pass<0>(v, lds);
+  }
+
+  // Calls fn(q, Z[f], Z[(N - f) mod N]) for every owned point f = t + T q.  The partner
+  // point is owned by another thread; it is fetched through LDS in two rounds (partners in
+  // the upper half of the index range, then in the lower half), so that only N/2 complex
+  // values are ever staged and no thread has to hold a second copy of its points.
+  template <class Fn>
+  __device__ __forceinline__ static void with_mirror(const float2 (&v)[E], float* lds, Fn fn) {
+    float2* l2 = reinterpret_cast<float2*>(lds);
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int upper = 1; upper >= 0; --upper) {
+#pragma unroll
+      for (int q = 0; q < E; ++q)
+        if ((q >= E / 2) == (upper != 0)) l2[t + T * q - upper * (N / 2)] = v[q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int m = (N - (t + T * q)) & (N - 1);
+        if ((m >= N / 2) == (upper != 0)) fn(q, v[q], l2[m - upper * (N / 2)]);
+      }
+      __syncthreads();
+    }
+  }
+};
+
+}  // namespace fdd

@@ -1,0 +1,105 @@
+// Phasor sum on the vector ALUs (Eqs. 4 and 7), any number of chunks, FP32.
+//
+//     Y[dm, k, f] = sum_c X[c, k, f] * exp(+2 pi i f tau[dm, c] / L)
+//
+// For one spin-frequency bin this is a matrix-vector product per chunk (Sec. 2.3); with a
+// single chunk nothing is shared along the chunk axis, so this kernel is the path for the
+// single-transform workloads, and the fallback for any shape.  Each thread owns one DM and
+// FV consecutive bins.  Per channel it derives the exact 64-bit phase increment of its delay,
+// evaluates the phasor of its first bin and of one bin step with sincos_turn, and walks the
+// remaining bins by complex multiplication (at most FV-1 steps, so the recurrence error stays
+// at a few float32 ulps).  Threads of a block that share bins read the same data from L1.
+//
+// With P set, the epilogue writes power spectra |Y|^2 for bins below L/2 (Sec. 5) instead of
+// the complex result.
+#include "device_math.h"
+#include "fdd_internal.h"
+
+namespace fdd {
+
+namespace {
+constexpr int kBinThreads = 64;   // threads along bins per block
+constexpr int kDmThreads = 4;     // threads along DMs per block
+}
+
+template <int FV, int NK>
+__global__ __launch_bounds__(256) void k_phasor_valu(PhasorArgs a) {
+  const int tx = threadIdx.x % kBinThreads;
+  const int ty = threadIdx.x / kBinThreads;
+  const int f0 = (blockIdx.x * kBinThreads + tx) * FV;
+  const int dm = blockIdx.y * kDmThreads + ty;
+  const int k0 = blockIdx.z * NK;
+  if (dm >= a.n_dm || f0 >= a.n_bins) return;   // no barriers in this kernel
+  const double dmv = a.dms[dm];
+  float2 acc[NK][FV];
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+    for (int i = 0; i < FV; ++i) acc[kk][i] = make_float2(0.0f, 0.0f);
+
+  int nk = a.n_chunks - k0;
+  if (nk > NK) nk = NK;
+  for (int c = 0; c < a.n_chan; ++c) {
+    const PhaseInc inc = phase_increment(dmv * a.kappa[c], a.log_len, a.mode);
+    float s, co;
+    sincos_turn(phase_at(inc, (uint32_t)f0), &s, &co);
+    float2 w = make_float2(co, s);
+    sincos_turn(inc.hi, &s, &co);
+    const float2 step = make_float2(co, s);
+    const float2* xr = a.X + ((int64_t)c * a.n_chunks + k0) * a.pitch + f0;
+#pragma unroll
+    for (int i = 0; i < FV; ++i) {
+#pragma unroll
+      for (int kk = 0; kk < NK; ++kk) {
+        if (kk < nk) {
+          const float2 x = xr[(int64_t)kk * a.pitch + i];
+          acc[kk][i].x = fmaf(w.x, x.x, fmaf(-w.y, x.y, acc[kk][i].x));
+          acc[kk][i].y = fmaf(w.x, x.y, fmaf(w.y, x.x, acc[kk][i].y));
+        }
+      }
+      w = cmul(w, step);
+    }
+  }
+
+  if (a.P != nullptr) {
+    if (f0 == 0) acc[0][0].x += a.dc_add;
+#pragma unroll
+    for (int i = 0; i < FV; ++i) {
+      const int f = f0 + i;
+      if (f < a.n_pow_bins)
+        a.P[(int64_t)dm * a.n_pow_bins + f] = fmaf(acc[0][i].x, acc[0][i].x, acc[0][i].y * acc[0][i].y);
+    }
+    return;
+  }
+#pragma unroll
+  for (int kk = 0; kk < NK; ++kk) {
+    if (kk < nk) {
+      const int64_t row = ((int64_t)dm * a.n_chunks + k0 + kk) * a.pitch;
+#pragma unroll
+      for (int i = 0; i < FV; ++i) {
+        const int f = f0 + i;
+        if (f < a.n_bins) {
+          a.Yr[row + f] = acc[kk][i].x;
+          a.Yi[row + f] = acc[kk][i].y;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_phasor_valu(const PhasorArgs& a, hipStream_t st) {
+  constexpr int FV = 16;
+  dim3 block(kBinThreads * kDmThreads);
+  const unsigned gx = (unsigned)((a.n_bins + kBinThreads * FV - 1) / (kBinThreads * FV));
+  const unsigned gy = (unsigned)((a.n_dm + kDmThreads - 1) / kDmThreads);
+  if (a.n_chunks == 1 || a.P != nullptr) {
+    hipLaunchKernelGGL((k_phasor_valu<FV, 1>), dim3(gx, gy, 1), block, 0, st, a);
+  } else {
+    constexpr int NK = 4;
+    const unsigned gz = (unsigned)((a.n_chunks + NK - 1) / NK);
+    hipLaunchKernelGGL((k_phasor_valu<FV, NK>), dim3(gx, gy, gz), block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fdd

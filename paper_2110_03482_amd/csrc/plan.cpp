@@ -1,0 +1,311 @@
+// Host planner and C ABI of the Fourier-domain dedispersion library.
+//
+// The planner validates a descriptor, forms the float64 delay per unit DM of every channel
+// (Eq. 1 divided by the sampling time), sizes the overlap-save chunking (Sec. 2.2: at least
+// the maximum delay is discarded at the end of every transformed series), builds the
+// twiddle table and lays out one workspace.  Execution enqueues, on one stream and without
+// host synchronisation, the stages of Algorithm 1: transpose/unpack (8-bit input only),
+// forward FFT per channel and chunk, phasor sum, and either the inverse FFT with scaling and
+// discard, or power spectra.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "fdd_internal.h"
+
+namespace fdd {
+
+namespace {
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool mul_ok(size_t a, size_t b, size_t* out) {
+  if (a != 0 && b > std::numeric_limits<size_t>::max() / a) return false;
+  *out = a * b;
+  return true;
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+fdd_status fail(fdd_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+fdd_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return FDD_E_DEVICE;
+}
+
+// Eq. 1 in samples per unit DM; the operation order is part of the ABI contract.
+static double kappa_of(double f_mhz, double ref_mhz, double tsamp_s) {
+  const double inv_f2 = 1.0 / (f_mhz * f_mhz);
+  const double inv_ref2 = 1.0 / (ref_mhz * ref_mhz);
+  return (FDD_K_DM * (inv_f2 - inv_ref2)) / tsamp_s;
+}
+
+static fdd_status upload_tables(fdd_plan_s* p) {
+  const WorkspaceLayout& w = p->ws;
+  std::vector<float2> tw((size_t)p->L);
+  for (int64_t j = 0; j < p->L; ++j) {
+    // exp(-2 pi i j / L) in float64, reduced to the first octant by symmetry for accuracy
+    const double a = -2.0 * M_PI * (double)j / (double)p->L;
+    tw[(size_t)j] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), w.tw_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddles)");
+  e = hipMemcpy(p->d_ws + w.dms, p->dms.data(), p->dms.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(dms)");
+  e = hipMemcpy(p->d_ws + w.kappa, p->kappa.data(), p->kappa.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(kappa)");
+  return FDD_OK;
+}
+
+static fdd_status layout(fdd_plan_s* p) {
+  WorkspaceLayout& w = p->ws;
+  const fdd_plan_desc& d = p->desc;
+  size_t off = 0, tmp = 0;
+  auto put = [&](size_t* at, size_t bytes) {
+    *at = off;
+    off = align_up(off + bytes);
+  };
+  w.tw_bytes = (size_t)p->L * sizeof(float2);
+  put(&w.tw, w.tw_bytes);
+  w.dms_bytes = (size_t)d.n_dm * sizeof(double);
+  put(&w.dms, w.dms_bytes);
+  w.kappa_bytes = (size_t)d.n_chan * sizeof(double);
+  put(&w.kappa, w.kappa_bytes);
+  w.scale_bytes = (size_t)p->n_chunks * sizeof(float);
+  put(&w.scale, w.scale_bytes);
+  if (d.input == FDD_IN_U8_TIME_MAJOR) {
+    if (!mul_ok((size_t)d.n_chan, (size_t)d.n_samp, &w.xt_bytes)) return fail(FDD_E_NOMEM, "input size overflows");
+    put(&w.xt, w.xt_bytes);
+  }
+  size_t rows = 0;
+  if (!mul_ok((size_t)d.n_chan, (size_t)p->n_chunks, &rows) || !mul_ok(rows, (size_t)p->pitch, &tmp) ||
+      !mul_ok(tmp, sizeof(float2), &w.X_bytes))
+    return fail(FDD_E_NOMEM, "Fourier-domain input size overflows");
+  put(&w.X, w.X_bytes);
+  if (!mul_ok((size_t)d.n_dm, (size_t)p->n_chunks, &rows) || !mul_ok(rows, (size_t)p->pitch, &tmp) ||
+      !mul_ok(tmp, sizeof(float), &w.Y_bytes))
+    return fail(FDD_E_NOMEM, "Fourier-domain output size overflows");
+  put(&w.Yr, w.Y_bytes);
+  put(&w.Yi, w.Y_bytes);
+  w.total = off;
+  return FDD_OK;
+}
+
+}  // namespace fdd
+
+using namespace fdd;
+
+extern "C" {
+
+const char* fdd_version(void) { return "fdd-gfx950 0.1"; }
+
+const char* fdd_status_string(fdd_status s) {
+  switch (s) {
+    case FDD_OK: return "ok";
+    case FDD_E_INVALID: return "invalid argument";
+    case FDD_E_OVERLAP: return "overlap does not cover the maximum delay";
+    case FDD_E_UNSUPPORTED: return "unsupported configuration";
+    case FDD_E_NOMEM: return "out of memory";
+    case FDD_E_DEVICE: return "device error";
+    case FDD_E_WORKSPACE: return "workspace missing or too small";
+  }
+  return "unknown status";
+}
+
+const char* fdd_last_error(void) { return g_last_error.c_str(); }
+
+fdd_status fdd_dispersion_delays(int32_t n_chan, const double* freqs, double ref, double tsamp, double dm,
+                                 double* tau_out) {
+  if (n_chan < 1 || freqs == nullptr || tau_out == nullptr) return fail(FDD_E_INVALID, "null or empty arguments");
+  if (!(tsamp > 0.0) || !(ref > 0.0) || !std::isfinite(dm)) return fail(FDD_E_INVALID, "bad tsamp, reference or DM");
+  for (int32_t c = 0; c < n_chan; ++c) tau_out[c] = dm * kappa_of(freqs[c], ref, tsamp);
+  return FDD_OK;
+}
+
+fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
+  if (desc == nullptr || out == nullptr) return fail(FDD_E_INVALID, "null descriptor or output");
+  *out = nullptr;
+  const fdd_plan_desc& d = *desc;
+  if (d.n_chan < 1 || d.n_dm < 1 || d.n_samp < 1) return fail(FDD_E_INVALID, "n_chan, n_dm and n_samp must be >= 1");
+  if (d.chan_freq_mhz == nullptr || d.dm == nullptr) return fail(FDD_E_INVALID, "null frequency or DM array");
+  if (!(d.tsamp_s > 0.0) || !std::isfinite(d.tsamp_s)) return fail(FDD_E_INVALID, "tsamp must be finite and > 0");
+  if (!(d.ref_freq_mhz > 0.0) || !std::isfinite(d.ref_freq_mhz)) return fail(FDD_E_INVALID, "bad reference frequency");
+  if (d.input != FDD_IN_U8_TIME_MAJOR && d.input != FDD_IN_F32_CHAN_MAJOR) return fail(FDD_E_INVALID, "bad input kind");
+  if (d.precision < FDD_FP32 || d.precision > FDD_BF16_SPLIT) return fail(FDD_E_INVALID, "bad precision");
+  if (d.delay_mode != FDD_DELAY_EXACT && d.delay_mode != FDD_DELAY_ROUND) return fail(FDD_E_INVALID, "bad delay mode");
+  const int64_t L = d.chunk_len;
+  if (L < 64 || (L & (L - 1)) != 0) return fail(FDD_E_INVALID, "chunk_len must be a power of two >= 64");
+  if (L > (int64_t(1) << 16)) return fail(FDD_E_UNSUPPORTED, "chunk_len above 2^16 is not supported by this build");
+  for (int32_t c = 0; c < d.n_chan; ++c) {
+    const double f = d.chan_freq_mhz[c];
+    if (!(f > 0.0) || !std::isfinite(f)) return fail(FDD_E_INVALID, "channel frequencies must be finite and > 0");
+    if (f > d.ref_freq_mhz) return fail(FDD_E_INVALID, "a channel lies above the reference frequency (negative delay)");
+  }
+  for (int32_t m = 0; m < d.n_dm; ++m) {
+    const double v = d.dm[m];
+    if (!(v >= 0.0) || !std::isfinite(v)) return fail(FDD_E_INVALID, "DMs must be finite and >= 0");
+  }
+
+  fdd_plan_s* p = new (std::nothrow) fdd_plan_s();
+  if (p == nullptr) return fail(FDD_E_NOMEM, "host allocation failed");
+  p->desc = d;
+  p->freqs.assign(d.chan_freq_mhz, d.chan_freq_mhz + d.n_chan);
+  p->dms.assign(d.dm, d.dm + d.n_dm);
+  p->desc.chan_freq_mhz = p->freqs.data();
+  p->desc.dm = p->dms.data();
+  p->kappa.resize((size_t)d.n_chan);
+  double kmax = 0.0, dmax = 0.0;
+  for (int32_t c = 0; c < d.n_chan; ++c) {
+    p->kappa[(size_t)c] = kappa_of(p->freqs[(size_t)c], d.ref_freq_mhz, d.tsamp_s);
+    kmax = std::max(kmax, p->kappa[(size_t)c]);
+  }
+  for (int32_t m = 0; m < d.n_dm; ++m) dmax = std::max(dmax, p->dms[(size_t)m]);
+  // tau = DM * kappa is monotone in both factors (both >= 0), so this is the largest delay.
+  p->max_tau = dmax * kmax;
+  p->L = L;
+  p->log_len = 0;
+  while ((int64_t(1) << p->log_len) < L) ++p->log_len;
+  p->n_bins = L / 2 + 1;
+  p->pitch = (p->n_bins + 63) / 64 * 64;
+  const int64_t need = (int64_t)std::ceil(p->max_tau);
+  if (d.single_chunk) {
+    if (d.n_samp > L) {
+      delete p;
+      return fail(FDD_E_INVALID, "single-chunk mode needs n_samp <= chunk_len");
+    }
+    p->S = L;
+    p->D = 0;
+    p->n_chunks = 1;
+  } else {
+    p->D = d.overlap > 0 ? d.overlap : need;
+    if (p->D < need) {
+      delete p;
+      return fail(FDD_E_OVERLAP, "overlap " + std::to_string(d.overlap) + " is shorter than ceil(max delay) = " +
+                                     std::to_string(need));
+    }
+    if (p->D >= L) {
+      delete p;
+      return fail(FDD_E_OVERLAP, "overlap must be shorter than chunk_len; use a longer chunk");
+    }
+    p->S = L - p->D;
+    p->n_chunks = (d.n_samp + p->S - 1) / p->S;
+  }
+  p->n_valid = d.n_samp - need > 0 ? d.n_samp - need : 0;
+  if (p->n_chunks > 65535 || d.n_dm > 65535 * 4 || d.n_chan > 65535) {
+    delete p;
+    return fail(FDD_E_UNSUPPORTED, "grid dimension limit exceeded");
+  }
+  p->kernel = (d.precision == FDD_FP32 && phasor_mfma_f32_supported((int)p->n_chunks)) ? "mfma_f32" : "valu";
+  if (d.precision != FDD_FP32) {
+    delete p;
+    return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums are not built yet");
+  }
+  fdd_status st = layout(p);
+  if (st != FDD_OK) {
+    delete p;
+    return st;
+  }
+  p->dry_run = (d.flags & FDD_PLAN_DRY_RUN) != 0;
+  if (!p->dry_run && !(d.flags & FDD_PLAN_EXTERNAL_WORKSPACE)) {
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, p->ws.total);
+    if (e != hipSuccess) {
+      delete p;
+      (void)hipGetLastError();
+      return fail(FDD_E_NOMEM, std::string("hipMalloc(workspace): ") + hipGetErrorString(e));
+    }
+    p->d_ws = (uint8_t*)mem;
+    p->ws_owned = true;
+    st = upload_tables(p);
+    if (st != FDD_OK) {
+      (void)hipFree(mem);
+      delete p;
+      return st;
+    }
+  }
+  *out = p;
+  return FDD_OK;
+}
+
+fdd_status fdd_plan_info(fdd_plan_t p, fdd_plan_geometry* g) {
+  if (p == nullptr || g == nullptr) return fail(FDD_E_INVALID, "null plan or output");
+  g->chunk_len = p->L;
+  g->stride = p->S;
+  g->overlap = p->D;
+  g->n_chunks = p->n_chunks;
+  g->n_bins = p->n_bins;
+  g->bins_padded = p->pitch;
+  g->max_delay = p->max_tau;
+  g->n_valid = p->n_valid;
+  g->workspace_bytes = p->ws.total;
+  return FDD_OK;
+}
+
+fdd_status fdd_plan_delays(fdd_plan_t p, double* tau) {
+  if (p == nullptr || tau == nullptr) return fail(FDD_E_INVALID, "null plan or output");
+  const size_t nc = p->kappa.size();
+  for (size_t m = 0; m < p->dms.size(); ++m)
+    for (size_t c = 0; c < nc; ++c) tau[m * nc + c] = p->dms[m] * p->kappa[c];
+  return FDD_OK;
+}
+
+const char* fdd_plan_kernel(fdd_plan_t p) { return p == nullptr ? "" : p->kernel.c_str(); }
+
+fdd_status fdd_set_workspace(fdd_plan_t p, void* mem, size_t bytes) {
+  if (p == nullptr || mem == nullptr) return fail(FDD_E_INVALID, "null plan or workspace");
+  if (p->dry_run) return fail(FDD_E_INVALID, "dry-run plans cannot take a workspace");
+  if (bytes < p->ws.total) return fail(FDD_E_WORKSPACE, "workspace too small: need " + std::to_string(p->ws.total));
+  if (((uintptr_t)mem % kAlign) != 0) return fail(FDD_E_INVALID, "workspace must be 256-byte aligned");
+  if (p->ws_owned) {
+    (void)hipFree(p->d_ws);
+    p->ws_owned = false;
+  }
+  p->d_ws = (uint8_t*)mem;
+  return upload_tables(p);
+}
+
+fdd_status fdd_destroy(fdd_plan_t p) {
+  if (p == nullptr) return FDD_OK;
+  if (p->ws_owned) (void)hipFree(p->d_ws);
+  for (auto& e : p->ev)
+    if (e != nullptr) (void)hipEventDestroy(e);
+  delete p;
+  return FDD_OK;
+}
+
+fdd_status fdd_profile_enable(fdd_plan_t p, int32_t enable) {
+  if (p == nullptr) return fail(FDD_E_INVALID, "null plan");
+  if (p->dry_run) return fail(FDD_E_INVALID, "dry-run plan");
+  if (enable && p->ev[0] == nullptr) {
+    for (auto& e : p->ev) {
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+    }
+  }
+  p->profile = enable != 0;
+  return FDD_OK;
+}
+
+fdd_status fdd_profile_read(fdd_plan_t p, float ms[4]) {
+  if (p == nullptr || ms == nullptr) return fail(FDD_E_INVALID, "null plan or output");
+  for (int i = 0; i < 4; ++i) ms[i] = 0.0f;
+  if (!p->profile) return fail(FDD_E_INVALID, "profiling is not enabled");
+  for (int i = 0; i < 4; ++i) {
+    if (!p->ev_recorded[i] || !p->ev_recorded[i + 1]) continue;
+    hipError_t r = hipEventSynchronize(p->ev[i + 1]);
+    if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+    r = hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]);
+    if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+  }
+  return FDD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+"""C-ABI checks that need no GPU: exported symbols, dry-run planning, validation errors.
+
+The planner's float64 delays and chunk geometry are compared with the oracle's own
+implementation of Eq. 1 and the Sec. 2.2 discard rule.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+fdd = pytest.importorskip("paper_2110_03482_amd")
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "fdd.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = fdd.library()
+    declared = _declared_functions()
+    assert "fdd_plan" in declared and "fdd_execute" in declared and "fdd_power_spectrum" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(fdd.exported_symbols()) >= set(declared)
+    assert fdd.fdd_version().startswith("fdd-gfx950")
+
+
+def _dry(w, **kw):
+    args = dict(overlap=w.overlap, single_chunk=w.single_chunk, input=w.input_kind, dry_run=True)
+    args.update(kw)
+    return fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, **args)
+
+
+@pytest.mark.parametrize("maker", [W.small_fp32, W.paper_shaped_u8, W.periodicity])
+def test_dry_run_delays_equal_oracle(maker):
+    w = maker()
+    p = _dry(w) if w.chunk_len <= (1 << 16) else None
+    tau_o = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+    one = fdd.fdd_dispersion_delays(w.freqs, w.ref_freq_mhz, w.tsamp_s, float(w.dms[-1]))
+    np.testing.assert_array_equal(one, tau_o[-1])
+    if p is None:
+        return
+    tau = p.delays()
+    np.testing.assert_array_equal(tau, tau_o)
+    np.testing.assert_array_equal(O.nearest_sample(tau), O.nearest_sample(tau_o))
+    p.close()
+
+
+def test_dry_run_geometry_paper_shaped():
+    w = W.paper_shaped_u8()
+    p = _dry(w)
+    g = p.geometry
+    tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+    S, n, D = O.chunk_geometry(w.n_samp, w.chunk_len, 0, False, float(tau.max()))
+    assert (g.stride, g.n_chunks, g.overlap) == (S, n, D)
+    assert g.n_bins == w.chunk_len // 2 + 1
+    assert g.bins_padded % 64 == 0 and g.bins_padded >= g.n_bins
+    assert g.max_delay == pytest.approx(float(tau.max()), rel=0, abs=0)
+    assert g.n_valid == w.n_samp - int(np.ceil(tau.max()))
+    # X (c64) + two Y planes (f32) + transposed input dominate the workspace
+    expect = (w.n_chan * n * g.bins_padded * 8 + 2 * w.n_dm * n * g.bins_padded * 4 + w.n_chan * w.n_samp)
+    assert expect <= g.workspace_bytes < expect + (1 << 24)
+    assert p.kernel == "mfma_f32"
+    p.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dry_run_geometry_random(seed):
+    rng = np.random.default_rng(seed)
+    L = int(2 ** rng.integers(8, 14))
+    w = W.tiny_random(seed, n_chan=int(rng.integers(1, 40)), n_samp=int(rng.integers(100, 20000)),
+                      n_dm=int(rng.integers(1, 50)), chunk_len=L, single_chunk=False, dm_max=float(rng.uniform(0.5, 5)))
+    tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+    try:
+        S, n, D = O.chunk_geometry(w.n_samp, L, 0, False, float(tau.max()))
+    except ValueError:
+        with pytest.raises(fdd.FddError):
+            _dry(w)
+        return
+    g = _dry(w).geometry
+    assert (g.stride, g.n_chunks, g.overlap) == (S, n, D)
+
+
+def _desc_kwargs():
+    w = W.small_fp32()
+    return w, dict(input="f32", dry_run=True)
+
+
+def test_validation_errors():
+    w = W.paper_shaped_u8()
+    with pytest.raises(fdd.FddError) as e:
+        _dry(w, overlap=14000)
+    assert e.value.status == 2                                     # FDD_E_OVERLAP
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, 1400.0, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, dry_run=True)
+    assert e.value.status == 1 and "reference" in str(e.value)
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, 3000, dry_run=True)
+    assert e.value.status == 1
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, 1 << 17, dry_run=True)
+    assert e.value.status == 3
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, 5000, 4096, single_chunk=True, dry_run=True)
+    assert e.value.status == 1
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, np.array([1.0, -2.0]), w.n_samp, w.chunk_len, dry_run=True)
+    assert e.value.status == 1
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, w.ref_freq_mhz, -1.0, w.dms, w.n_samp, w.chunk_len, dry_run=True)
+    assert e.value.status == 1
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, 1 << 16, overlap=1 << 16, dry_run=True)
+    assert e.value.status == 2
+
+
+def test_null_and_dry_run_execution_rejected():
+    lib = fdd.library()
+    assert lib.fdd_plan(None, None) == 1
+    assert lib.fdd_execute(None, None, None, None) == 1
+    assert lib.fdd_plan_info(None, None) == 1
+    assert lib.fdd_destroy(None) == 0
+    w = W.small_fp32()
+    p = _dry(w)
+    st = lib.fdd_execute(p.handle, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
+    assert st == 1 and "dry-run" in fdd.fdd_last_error()
+    assert lib.fdd_set_workspace(p.handle, ctypes.c_void_p(256), ctypes.c_size_t(1 << 30)) == 1
+    p.close()
+    assert fdd.fdd_status_string(2).startswith("overlap")
+
+
+def test_kernel_selection():
+    w = W.small_fp32()
+    assert _dry(w).kernel == "valu"                      # one chunk: matrix-vector shape
+    w2 = W.tiny_random(1, 16, 5000, 8, 1024, False, dm_max=3.0)
+    p = _dry(w2)
+    assert p.geometry.n_chunks >= 3 and p.kernel == "mfma_f32"

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
+
+Tolerance (FP32 path): per DM row, ||y - y_ref||_2 / ||y_ref||_2 <= 1e-5.  For 8-bit input the
+rows also carry the 128 x n_chan zero-point offset, so the error is additionally checked
+against the mean-removed row norm, whose floor is set by float32 storage of values near
+128 x n_chan (half an ulp of 2^17 is 2^-7), bounded here at 4e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fdd = pytest.importorskip("paper_2110_03482_amd")
+
+TOL = 1e-5
+
+
+def rel_err(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    num = np.linalg.norm(y - ref, axis=-1)
+    return num / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+
+
+def rel_err_centred(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    num = np.linalg.norm(y - ref, axis=-1)
+    den = np.linalg.norm(ref - ref.mean(axis=-1, keepdims=True), axis=-1)
+    return num / np.maximum(den, 1e-300)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def run_gpu(w, x, mode, power=False):
+    with fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, overlap=w.overlap,
+                  single_chunk=w.single_chunk, input=w.input_kind, mode=mode) as p:
+        xd = to_dev(x)
+        out = p.power_spectrum(xd) if power else p.execute(xd)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), p.kernel, p.geometry
+
+
+def run_oracle(w, x, mode, rows=None):
+    return O.fdd(x, w.input_kind, w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, overlap=w.overlap,
+                 single_chunk=w.single_chunk, mode=mode, rows=rows)
+
+
+def small_input(seed=0):
+    w = W.small_fp32(seed)
+    x = W.gaussian_f32(w.n_chan, w.n_samp, seed)
+    offs = O.nearest_sample(O.delays([30.0], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
+    W.inject_pulse_f32(x, offs, 1000, 5.0, circular=True)
+    return w, x
+
+
+# ----------------------------------------------------------------------------- small workload
+
+@pytest.mark.parametrize("mode", ["exact", "round"])
+def test_small_matches_oracle(mode):
+    w, x = small_input()
+    print(f"small workload, mode={mode}", flush=True)
+    y, kernel, _ = run_gpu(w, x, mode)
+    ref = run_oracle(w, x, mode)
+    err = rel_err(y, ref)
+    print(f"kernel={kernel} max rel err {err.max():.3e}")
+    assert err.max() <= TOL
+    assert int(np.argmax(y[:, 1000])) == 30
+
+
+def test_small_round_equals_circular_tdd():
+    w, x = small_input(1)
+    y, _, _ = run_gpu(w, x, "round")
+    d = O.nearest_sample(O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s))
+    ref = O.tdd(x, "f32", d, circular_len=w.chunk_len)
+    assert rel_err(y, ref).max() <= TOL
+
+
+def test_dm_zero_row_is_channel_sum():
+    w, x = small_input(2)
+    y, _, _ = run_gpu(w, x, "exact")
+    ref = x.astype(np.float64).sum(axis=0)
+    assert rel_err(y[0], ref) <= TOL
+
+
+@pytest.mark.parametrize("n_dm", [256, 1024])
+def test_precision_sweep_workload_fp32(n_dm):
+    w = W.precision_sweep(n_dm)
+    x = W.gaussian_f32(w.n_chan, w.n_samp, 0)
+    y, _, _ = run_gpu(w, x, "exact")
+    rows = list(range(0, n_dm, max(1, n_dm // 64)))
+    ref = run_oracle(w, x, "exact", rows=rows)
+    assert rel_err(y[rows], ref).max() <= TOL
+
+
+# ----------------------------------------------------------------------------- chunked shapes
+
+CHUNKED = [
+    # n_chan, n_samp, n_dm, L, kind, dm_max          chunks: VALU (1-2) and MFMA (>= 3) paths
+    (8, 3000, 5, 4096, "f32", 20.0),      # 1 chunk + ragged (VALU)
+    (16, 6000, 9, 4096, "f32", 20.0),     # 2 chunks (VALU)
+    (13, 20000, 70, 2048, "f32", 10.0),   # many chunks, odd channel count, DM tile ragged (MFMA)
+    (64, 50001, 64, 8192, "u8", 40.0),    # 8-bit input, ragged tail (MFMA)
+    (32, 30000, 130, 4096, "u8", 25.0),   # (MFMA, 3 DM tiles)
+    (40, 9000, 33, 1024, "f32", 3.0),     # short chunks, many of them (MFMA, 2 column tiles)
+    (5, 700, 3, 64, "f32", 0.05),         # shortest transform
+]
+
+
+@pytest.mark.parametrize("case", CHUNKED, ids=[f"{c[0]}ch_{c[1]}s_{c[2]}dm_L{c[3]}_{c[4]}" for c in CHUNKED])
+@pytest.mark.parametrize("mode", ["exact", "round"])
+def test_chunked_matches_oracle(case, mode):
+    n_chan, n_samp, n_dm, L, kind, dm_max = case
+    seed = n_chan * 7 + n_dm
+    w = W.tiny_random(seed, n_chan, n_samp, n_dm, L, single_chunk=False, input_kind=kind, dm_max=dm_max)
+    x = W.gaussian_u8(n_samp, n_chan, seed) if kind == "u8" else W.gaussian_f32(n_chan, n_samp, seed)
+    print(f"chunked case {case} mode={mode}", flush=True)
+    y, kernel, g = run_gpu(w, x, mode)
+    ref = run_oracle(w, x, mode)
+    err = rel_err(y, ref)
+    print(f"kernel={kernel} chunks={g.n_chunks} max rel err {err.max():.3e}")
+    assert err.max() <= TOL
+    if kind == "u8":
+        assert rel_err_centred(y, ref).max() <= 4e-5
+    if mode == "round":
+        d = O.nearest_sample(O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s))
+        assert rel_err(y, O.tdd(x, kind, d)).max() <= TOL
+
+
+def test_single_chunk_shorter_than_transform():
+    w = W.tiny_random(3, 12, 2500, 17, 4096, single_chunk=True)
+    x = W.gaussian_f32(w.n_chan, w.n_samp, 3)
+    for mode in ("exact", "round"):
+        y, _, _ = run_gpu(w, x, mode)
+        assert rel_err(y, run_oracle(w, x, mode)).max() <= TOL
+
+
+def test_single_channel_single_dm():
+    w = W.tiny_random(4, 1, 4096, 1, 4096, single_chunk=True)
+    x = W.gaussian_f32(1, 4096, 4)
+    y, _, _ = run_gpu(w, x, "exact")
+    assert rel_err(y, run_oracle(w, x, "exact")).max() <= TOL
+
+
+# ----------------------------------------------------------------------------- power spectra
+
+@pytest.mark.parametrize("mode", ["exact", "round"])
+def test_power_spectrum_small(mode):
+    w, x = small_input(5)
+    P, _, _ = run_gpu(w, x, mode, power=True)
+    tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+    ref = O.oracle_fdd_rows(x, "f32", tau, w.chunk_len, w.chunk_len, 1, True, mode, power=True)
+    # power is quadratic: its relative error is twice that of the amplitudes
+    assert rel_err(P, ref).max() <= 2 * TOL
+
+
+def test_power_spectrum_u8_full_transform():
+    w = W.tiny_random(6, 24, 8192, 40, 8192, single_chunk=True, input_kind="u8")
+    x = W.gaussian_u8(w.n_samp, w.n_chan, 6)
+    P, _, _ = run_gpu(w, x, "exact", power=True)
+    tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+    ref = O.oracle_fdd_rows(x, "u8", tau, w.chunk_len, w.chunk_len, 1, True, "exact", power=True)
+    assert rel_err(P[:, 1:], ref[:, 1:]).max() <= 2 * TOL
+    np.testing.assert_allclose(P[:, 0], ref[:, 0], rtol=2e-6)
+
+
+def test_power_rejects_chunked_plan():
+    w = W.tiny_random(7, 8, 9000, 4, 1024, single_chunk=False, dm_max=2.0)
+    with fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len) as p:
+        x = to_dev(W.gaussian_f32(w.n_chan, w.n_samp, 7))
+        with pytest.raises(fdd.FddError) as e:
+            p.power_spectrum(x, out=torch.empty((w.n_dm, 512), device="cuda"))
+        assert e.value.status == 3
+
+
+# ----------------------------------------------------------------------------- paper-shaped, full size
+
+@pytest.fixture(scope="module")
+def paper_input():
+    w = W.paper_shaped_u8()
+    x = W.gaussian_u8(w.n_samp, w.n_chan, 0)
+    for dm, t0 in ((100.0, 1 << 18), (450.0, 1 << 19), (900.0, 3 << 18)):
+        offs = O.nearest_sample(O.delays([dm], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
+        W.inject_pulse_u8(x, offs, t0, 80.0)
+    return w, x
+
+
+def test_paper_shaped_sampled_rows(paper_input):
+    """1024 ch x 2^20 8-bit samples x 2048 DMs, L = 2^16 (21 chunks): rows checked against the oracle."""
+    w, x = paper_input
+    print("paper-shaped workload, exact mode", flush=True)
+    y, kernel, g = run_gpu(w, x, "exact")
+    assert kernel == "mfma_f32" and g.n_chunks == 21
+    rows = [0, 921]
+    ref = run_oracle(w, x, "exact", rows=rows)
+    err = rel_err(y[rows], ref)
+    errc = rel_err_centred(y[rows], ref)
+    print(f"rows {rows}: rel err {err}, centred {errc}")
+    assert err.max() <= TOL and errc.max() <= 4e-5
+    # properties over every row: finite, DM 0 is the channel sum, pulses found at their trials
+    assert np.isfinite(y).all()
+    for trial, t0 in ((205, 1 << 18), (921, 1 << 19), (1842, 3 << 18)):
+        win = y[:, t0 - 2: t0 + 3].max(axis=1)
+        assert abs(int(np.argmax(win)) - trial) <= 2, (trial, int(np.argmax(win)))
+
+
+def test_paper_shaped_round_vs_tdd(paper_input):
+    w, x = paper_input
+    y, _, _ = run_gpu(w, x, "round")
+    rows = [1, 1842, 2047]
+    d = O.nearest_sample(O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s))
+    ref = O.tdd(x, "u8", d, rows=rows)
+    err = rel_err(y[rows], ref)
+    print(f"round rows {rows}: rel err {err}")
+    assert err.max() <= TOL
+    assert rel_err_centred(y[rows], ref).max() <= 4e-5
