@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the Fourier-domain dedispersion hot path on one MI355X.
+
+Workload (default): the paper-shaped problem of Sec. 4.1 at one GPU's size -- 1024 channels
+over 1250-1550 MHz, 64 us sampling, 2^20 8-bit samples (Gaussian, mean 128, sigma 16) with
+pulses injected at DM 100, 450 and 900, 2048 trial DMs from 0 to 1000, overlap-save chunks
+of L = 2^16 with overlap ceil(max delay) = 14496 (21 chunks).  One step = one fdd_execute:
+transpose/unpack, forward FFTs, phasor sum and inverse FFTs, input and output resident in HBM.
+
+Prints one JSON line:  value = N_DM * N_t / (seconds per step)  (DM-trial samples/s).
+The roofline object refers to the phasor-sum kernel, whose duration is the mean over the timed
+steps of HIP events recorded by the library on the execution stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBs": 8000.0,
+    "fp32_mfma_TFLOPs": 157.3,
+    "fp16_mfma_TFLOPs": 2500.0,
+    "bf16_mfma_TFLOPs": 2500.0,
+    "fp32_valu_TFLOPs": 157.3,
+}
+METRIC = "DM-trial samples/s (N_DM·N_t/s), FP32 FDD vs FP16-split MFMA at stated err"
+KERNEL_SOURCES = {
+    "mfma_f32": "paper_2110_03482_amd/csrc/phasor_mfma_f32.hip",
+    "valu": "paper_2110_03482_amd/csrc/phasor_valu.hip",
+}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest(rel: str) -> str:
+    with open(os.path.join(ROOT, rel), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it still matches."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    with open(path) as fh:
+        table = json.load(fh)
+    rec = table.get(f"{kernel}:{workload}")
+    if rec is None or rec.get("source_sha") != source_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_paper_input(w, fdd):
+    import workloads as W
+    log("generating 8-bit input (2^20 x 1024) ...")
+    x = W.gaussian_u8(w.n_samp, w.n_chan, w.seed)
+    for dm, t0 in ((100.0, 1 << 18), (450.0, 1 << 19), (900.0, 3 << 18)):
+        tau = fdd.fdd_dispersion_delays(w.freqs, w.ref_freq_mhz, w.tsamp_s, dm)
+        W.inject_pulse_u8(x, np.floor(tau + 0.5).astype(np.int64), t0, 80.0)
+    return x
+
+
+def cpu_baseline(w, x, mode: str):
+    """Time the FP64 oracle on a bounded sample: 4 DM rows over the first 4 chunks."""
+    import oracle as O
+    tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+    S, n_chunks, _ = O.chunk_geometry(w.n_samp, w.chunk_len, w.overlap, w.single_chunk, float(tau.max()))
+    k = 4
+    rows = [0, 205, 921, 1842]
+    n_s = k * S
+    xs = np.ascontiguousarray(x[:n_s])
+    log(f"cpu baseline: oracle on {len(rows)} DM rows x {k} chunks ({n_s} samples) ...")
+    t0 = time.perf_counter()
+    O.oracle_fdd_rows(xs, w.input_kind, tau[rows], w.chunk_len, S, k, False, mode)
+    dt = time.perf_counter() - t0
+    return {
+        "value": len(rows) * n_s / dt,
+        "unit": "DM-trial samples/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 oracle (numpy, single thread) on {len(rows)} of {w.n_dm} DM rows x {k} of "
+                  f"{n_chunks} chunks ({n_s} output samples per row) of the same workload; {dt:.1f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16_split", "bf16_split"])
+    ap.add_argument("--mode", default="exact", choices=["exact", "round"])
+    ap.add_argument("--n-dm", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "single-GPU build: the path would shard across GPUs by DM trials, "
+                                   "but only the one-GPU figure is measured; run with --gpus 1",
+                          "n_gpus": args.gpus}), flush=True)
+        return 2
+
+    import torch
+
+    import paper_2110_03482_amd as fdd
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        return 1
+    dev = torch.device("cuda:0")
+    if args.copy_probe_mib > 0:
+        # a plain copy of known size: calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters
+        n = args.copy_probe_mib << 20
+        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n}), flush=True)
+        return 0
+    w = W.paper_shaped_u8(0, n_dm=args.n_dm)
+    x = make_paper_input(w, fdd)
+    xd = torch.from_numpy(x).to(dev)
+    plan = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, overlap=w.overlap,
+                    single_chunk=w.single_chunk, input=w.input_kind, precision=args.precision, mode=args.mode,
+                    device=dev)
+    g = plan.geometry
+    out = torch.empty((w.n_dm, w.n_samp), dtype=torch.float32, device=dev)
+    log(f"plan: L={g.chunk_len} S={g.stride} D={g.overlap} chunks={g.n_chunks} kernel={plan.kernel} "
+        f"workspace={g.workspace_bytes / 2**30:.2f} GiB")
+
+    for i in range(args.warmup):
+        plan.execute(xd, out)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    plan.profile(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.execute(xd, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, n_prof = plan.stage_ms()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; stages {stage_ms} ({n_prof} calls)")
+
+    samples = w.n_dm * w.n_samp
+    value = samples / (ms_per_step * 1e-3)
+    flops = 8.0 * w.n_dm * w.n_chan * g.n_bins * g.n_chunks      # complex MACs of Eq. 7, 8 flops each
+    ps_ms = stage_ms[2]
+    achieved = flops / (ps_ms * 1e-3) / 1e12
+    peak = {"fp32": PEAK["fp32_mfma_TFLOPs"], "fp16_split": PEAK["fp16_mfma_TFLOPs"],
+            "bf16_split": PEAK["bf16_mfma_TFLOPs"]}[args.precision]
+    bound = "mfma" if plan.kernel.startswith("mfma") else "alu"
+    workload_name = w.name + f"_{args.mode}_{args.precision}"
+    traffic = measured_traffic(plan.kernel, workload_name)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DM-trial samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else ("f16x2+f32acc" if args.precision == "fp16_split"
+                                                          else "bf16x2+f32acc"),
+        "data": "synthetic",
+        "config": {
+            "workload": workload_name,
+            "n_chan": w.n_chan, "n_samp": w.n_samp, "n_dm": w.n_dm, "input": "u8 time-major",
+            "band_mhz": [w.f_lo_mhz, w.f_hi_mhz], "tsamp_s": w.tsamp_s, "dm_range": [0.0, float(w.dms[-1])],
+            "chunk_len": int(g.chunk_len), "overlap": int(g.overlap), "n_chunks": int(g.n_chunks),
+            "delay_mode": args.mode, "precision": args.precision, "phasor_kernel": plan.kernel,
+        },
+        "stages_ms": {"transpose": stage_ms[0], "forward_fft": stage_ms[1], "phasor_sum": stage_ms[2],
+                      "inverse_fft": stage_ms[3]},
+        "roofline": {
+            "kernel": f"phasor_sum_{plan.kernel}",
+            "bound": bound,
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": traffic,
+            "algorithmic_flops_per_launch": flops,
+        },
+    }
+    plan.close()
+    del xd, out
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, x, args.mode)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

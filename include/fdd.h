@@ -131,12 +131,14 @@ fdd_status fdd_power_spectrum(fdd_plan_t plan, const void* d_in, float* d_out, v
 /* Release a plan and the workspace it allocated itself (never a caller-owned one). */
 fdd_status fdd_destroy(fdd_plan_t plan);
 
-/* Stage timing.  With profiling enabled, fdd_execute / fdd_power_spectrum record HIP events
- * on their stream around each stage; fdd_profile_read waits for the last call's events and
- * returns milliseconds for [0] transpose/unpack, [1] forward FFT, [2] phasor sum,
- * [3] inverse FFT (0 for a stage that did not run). */
-fdd_status fdd_profile_enable(fdd_plan_t plan, int32_t enable);
-fdd_status fdd_profile_read(fdd_plan_t plan, float ms[4]);
+/* Stage timing.  fdd_profile_enable(plan, depth) with depth >= 1 makes fdd_execute /
+ * fdd_power_spectrum record HIP events on their stream around each stage, for the first
+ * `depth` calls after enabling or after the last read (depth 0 disables).  fdd_profile_read waits for the recorded events and
+ * returns the mean milliseconds per call for [0] transpose/unpack, [1] forward FFT,
+ * [2] phasor sum, [3] inverse FFT (0 for a stage that did not run), writes the number of
+ * calls averaged to *n_calls (may be NULL), and starts a new recording. */
+fdd_status fdd_profile_enable(fdd_plan_t plan, int32_t depth);
+fdd_status fdd_profile_read(fdd_plan_t plan, float ms[4], int32_t* n_calls);
 
 /* Host helpers. */
 /* tau (samples) of every channel at one DM, Eq. 1, exactly as plans compute it. */

@@ -87,7 +87,8 @@ _SIGNATURES = {
     "fdd_power_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "fdd_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
-    "fdd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)]),
+    "fdd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "fdd_dispersion_delays": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "fdd_plan_delays": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
@@ -170,14 +171,16 @@ def fdd_destroy(plan) -> None:
     _check(library().fdd_destroy(plan), "fdd_destroy")
 
 
-def fdd_profile_enable(plan, enable: bool) -> None:
-    _check(library().fdd_profile_enable(plan, int(bool(enable))), "fdd_profile_enable")
+def fdd_profile_enable(plan, depth: int) -> None:
+    _check(library().fdd_profile_enable(plan, int(depth)), "fdd_profile_enable")
 
 
-def fdd_profile_read(plan) -> list:
+def fdd_profile_read(plan):
+    """(mean ms per stage [transpose, forward FFT, phasor sum, inverse FFT], calls averaged)."""
     ms = (ctypes.c_float * 4)()
-    _check(library().fdd_profile_read(plan, ms), "fdd_profile_read")
-    return [float(v) for v in ms]
+    n = ctypes.c_int32()
+    _check(library().fdd_profile_read(plan, ms, ctypes.byref(n)), "fdd_profile_read")
+    return [float(v) for v in ms], int(n.value)
 
 
 def fdd_dispersion_delays(freqs_mhz: Sequence[float], ref_freq_mhz: float, tsamp_s: float, dm: float) -> np.ndarray:
@@ -297,11 +300,12 @@ class Plan:
         fdd_power_spectrum(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
         return out
 
-    def profile(self, enable: bool = True) -> None:
-        fdd_profile_enable(self._handle, enable)
+    def profile(self, depth: int = 1) -> None:
+        """Record per-stage HIP events for the next `depth` calls (0 disables)."""
+        fdd_profile_enable(self._handle, depth)
 
-    def stage_ms(self) -> list:
-        """[transpose, forward FFT, phasor sum, inverse FFT] of the last call, in ms."""
+    def stage_ms(self):
+        """Mean ms per call of [transpose, forward FFT, phasor sum, inverse FFT], and the call count."""
         return fdd_profile_read(self._handle)
 
     def close(self) -> None:

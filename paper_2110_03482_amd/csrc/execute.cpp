@@ -14,9 +14,12 @@ fdd_status check_ready(fdd_plan_t p, const void* in, const float* out) {
   return FDD_OK;
 }
 
+// Record stage boundary i (0..4) of the current call into the profiling ring.
 void mark(fdd_plan_t p, int i, hipStream_t st) {
-  if (!p->profile) return;
-  p->ev_recorded[i] = hipEventRecord(p->ev[i], st) == hipSuccess;
+  if (p->prof_depth == 0 || p->prof_calls >= p->prof_depth) return;
+  const size_t slot = (size_t)p->prof_calls * 5 + (size_t)i;
+  p->ev_ok[slot] = hipEventRecord(p->ev[slot], st) == hipSuccess;
+  if (i == 4) ++p->prof_calls;
 }
 
 fdd_status forward(fdd_plan_t p, const void* in, hipStream_t st) {
@@ -58,6 +61,7 @@ PhasorArgs phasor_args(fdd_plan_t p) {
   a.n_pow_bins = (int)(p->L / 2);
   a.log_len = p->log_len;
   a.mode = p->desc.delay_mode;
+  a.tile_variant = p->tile_variant;
   return a;
 }
 

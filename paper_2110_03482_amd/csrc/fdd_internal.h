@@ -45,6 +45,7 @@ struct PhasorArgs {
   int log_len = 0;                  // log2 L
   int mode = 0;                     // fdd_delay_mode
   float dc_add = 0.0f;              // added to Re Y at bin 0 before power (8-bit zero point)
+  int tile_variant = 0;             // matrix-core tile shape (0 = default)
 };
 
 hipError_t launch_transpose_u8(const uint8_t* in, uint8_t* out, int64_t n_samp, int n_chan, hipStream_t st);
@@ -79,10 +80,12 @@ struct fdd_plan_s {
   bool ws_owned = false;
   bool dry_run = false;
   std::string kernel = "valu";
-  // stage timing
-  bool profile = false;
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  bool ev_recorded[5] = {false, false, false, false, false};
+  int tile_variant = 0;                 // FDD_TILE_VARIANT override
+  // stage timing: a ring of `prof_depth` calls x 5 events
+  int prof_depth = 0;
+  int64_t prof_calls = 0;               // calls recorded since the last read
+  std::vector<hipEvent_t> ev;
+  std::vector<char> ev_ok;
 };
 
 namespace fdd {

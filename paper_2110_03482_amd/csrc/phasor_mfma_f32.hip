@@ -31,19 +31,21 @@ namespace fdd {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 namespace {
-constexpr int kFB = 16;     // bins per workgroup
-constexpr int kKC = 8;      // channels per LDS stage
-constexpr int kDmTile = 64; // DMs per workgroup
 constexpr int kXcds = 8;
 }  // namespace
 
-template <int NT>
+// FB bins per workgroup, KC channels per LDS stage, NT 16-column tiles (2N <= 16 NT),
+// MW 16-DM sub-tiles per wave (64 MW DMs per workgroup).
+template <int NT, int FB, int KC, int MW>
 __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt, int n_bb) {
+  constexpr int kDmTile = 64 * MW;
   constexpr int NCOL = NT * 16;
   // per-channel stride padded by 16 floats so that the four channels read by one MFMA step
   // fall in distinct LDS banks
-  constexpr int CST = kFB * NCOL + 16;
-  constexpr int PLANE = kKC * CST;
+  constexpr int CST = FB * NCOL + 16;
+  constexpr int PLANE = KC * CST;
+  // staging elements (float4 = two bins of one (channel, chunk)) per thread, for N <= 8 NT
+  constexpr int PER = (KC * 8 * NT * (FB / 2) + 255) / 256;
   __shared__ float bre[PLANE];
   __shared__ float bim[PLANE];
 
@@ -53,12 +55,12 @@ __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt
   const int bb = (slot / n_dmt) * kXcds + xcd;
   const int dmt = slot % n_dmt;
   if (bb >= n_bb) return;                     // uniform per workgroup, before any barrier
-  const int fb0 = bb * kFB;
+  const int fb0 = bb * FB;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int N = a.n_chunks;
-  const int ncol = 2 * N;
+  const int nel = KC * N * (FB / 2);
 
   // zero once: padding columns (>= 2N) are never written by the staging below
   for (int i = tid; i < PLANE; i += 256) {
@@ -66,107 +68,158 @@ __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt
     bim[i] = 0.0f;
   }
 
-  const int dm = dmt * kDmTile + wave * 16 + (lane & 15);
-  const double dmv = a.dms[dm < a.n_dm ? dm : a.n_dm - 1];
+  // Staging map, fixed for all channel blocks: element e = tid + 256 j is the float4 of bins
+  // (2 fp, 2 fp + 1) of chunk k of channel cl of the block.
+  int goff[PER], loff[PER], kk[PER], ccl[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j;
+    const int fp = e % (FB / 2);
+    const int k = (e / (FB / 2)) % N;
+    const int cl = e / ((FB / 2) * N);
+    goff[j] = (cl * N + k) * (int)a.pitch + fb0 + 2 * fp;     // in float2 units, < 2^31 for N <= 24
+    loff[j] = cl * CST + 2 * fp * NCOL + k;
+    kk[j] = k;
+    ccl[j] = e < nel ? cl : KC;                                 // KC marks "no element"
+  }
+  float4 pf[PER];
+  auto fetch = [&](int cb) {
+    const float2* base = a.X + (int64_t)cb * N * a.pitch;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      pf[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (ccl[j] < KC && cb + ccl[j] < a.n_chan) pf[j] = *(const float4*)(base + goff[j]);
+    }
+  };
+  auto deposit = [&]() {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (ccl[j] >= KC) continue;
+      const int i0 = loff[j];
+      const int i1 = i0 + NCOL;
+      const float4 v = pf[j];
+      bre[i0] = v.x;
+      bim[i0] = -v.y;
+      bre[i0 + N] = v.y;
+      bim[i0 + N] = v.x;
+      bre[i1] = v.z;
+      bim[i1] = -v.w;
+      bre[i1 + N] = v.w;
+      bim[i1 + N] = v.z;
+    }
+  };
+
+  double dmv[MW];
+#pragma unroll
+  for (int m = 0; m < MW; ++m) {
+    const int dm = dmt * kDmTile + (wave * MW + m) * 16 + (lane & 15);
+    dmv[m] = a.dms[dm < a.n_dm ? dm : a.n_dm - 1];
+  }
   const int cq = lane >> 4;
 
-  floatx4 acc[kFB][NT];
+  floatx4 acc[MW][FB][NT];
 #pragma unroll
-  for (int f = 0; f < kFB; ++f)
+  for (int m = 0; m < MW; ++m)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[f][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int f = 0; f < FB; ++f)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[m][f][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  for (int cb = 0; cb < a.n_chan; cb += kKC) {
+  fetch(0);
+  for (int cb = 0; cb < a.n_chan; cb += KC) {
+    __syncthreads();                          // the previous block's operands are consumed
+    deposit();
     __syncthreads();
-    // stage X[cb .. cb+KC)[0 .. N)[fb0 .. fb0+16) into the two operand planes
-    const int nel = kKC * N * (kFB / 2);
-    for (int e = tid; e < nel; e += 256) {
-      const int fp = e % (kFB / 2);
-      const int k = (e / (kFB / 2)) % N;
-      const int cl = e / ((kFB / 2) * N);
-      const int c = cb + cl;
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (c < a.n_chan) v = *(const float4*)(a.X + ((int64_t)c * N + k) * a.pitch + fb0 + 2 * fp);
-      const int i0 = cl * CST + 2 * fp * NCOL;
-      const int i1 = i0 + NCOL;
-      bre[i0 + k] = v.x;
-      bim[i0 + k] = -v.y;
-      bre[i0 + k + N] = v.y;
-      bim[i0 + k + N] = v.x;
-      bre[i1 + k] = v.z;
-      bim[i1 + k] = -v.w;
-      bre[i1 + k + N] = v.w;
-      bim[i1 + k + N] = v.z;
-    }
-    __syncthreads();
+    if (cb + KC < a.n_chan) fetch(cb + KC);   // in flight while this block computes
 #pragma unroll
-    for (int s = 0; s < kKC / 4; ++s) {
+    for (int s = 0; s < KC / 4; ++s) {
       const int cl = 4 * s + cq;
       int c = cb + cl;
-      if (c >= a.n_chan) c = a.n_chan - 1;      // its data were staged as zeros
-      const PhaseInc inc = phase_increment(dmv * a.kappa[c], a.log_len, a.mode);
-      float sn, cs;
-      sincos_turn(phase_at(inc, (uint32_t)fb0), &sn, &cs);
-      float2 w = make_float2(cs, sn);
-      sincos_turn(inc.hi, &sn, &cs);
-      const float2 step = make_float2(cs, sn);
-      float wr[kFB], wi[kFB];
-#pragma unroll
-      for (int f = 0; f < kFB; ++f) {
-        wr[f] = w.x;
-        wi[f] = w.y;
-        w = cmul(w, step);
-      }
+      if (c >= a.n_chan) c = a.n_chan - 1;    // its data were staged as zeros
+      const double kap = a.kappa[c];
       const float* pr = bre + cl * CST + (lane & 15);
       const float* pi = bim + cl * CST + (lane & 15);
 #pragma unroll
-      for (int f = 0; f < kFB; ++f)
+      for (int m = 0; m < MW; ++m) {
+        const PhaseInc inc = phase_increment(dmv[m] * kap, a.log_len, a.mode);
+        float sn, cs;
+        sincos_turn(phase_at(inc, (uint32_t)fb0), &sn, &cs);
+        float2 w = make_float2(cs, sn);
+        sincos_turn(inc.hi, &sn, &cs);
+        const float2 step = make_float2(cs, sn);
+        float wr[FB], wi[FB];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[f][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[f], pr[f * NCOL + 16 * nt], acc[f][nt], 0, 0, 0);
+        for (int f = 0; f < FB; ++f) {
+          wr[f] = w.x;
+          wi[f] = w.y;
+          w = cmul(w, step);
+        }
 #pragma unroll
-      for (int f = 0; f < kFB; ++f)
+        for (int f = 0; f < FB; ++f)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[f][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wi[f], pi[f * NCOL + 16 * nt], acc[f][nt], 0, 0, 0);
+          for (int nt = 0; nt < NT; ++nt)
+            acc[m][f][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[f], pr[f * NCOL + 16 * nt], acc[m][f][nt], 0, 0, 0);
+#pragma unroll
+        for (int f = 0; f < FB; ++f)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[m][f][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wi[f], pi[f * NCOL + 16 * nt], acc[m][f][nt], 0, 0, 0);
+      }
     }
   }
 
   // D[i][j] of a 16x16 tile sits in lane 16*(i/4) + j, register i%4.
 #pragma unroll
+  for (int m = 0; m < MW; ++m)
+#pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int n = 16 * nt + (lane & 15);
-    if (n >= ncol) continue;
+    if (n >= 2 * N) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int dmr = dmt * kDmTile + wave * 16 + 4 * (lane >> 4) + r;
+      const int dmr = dmt * kDmTile + (wave * MW + m) * 16 + 4 * (lane >> 4) + r;
       if (dmr >= a.n_dm) continue;
       float* dst = (n < N ? a.Yr + ((int64_t)dmr * N + n) * a.pitch
                           : a.Yi + ((int64_t)dmr * N + (n - N)) * a.pitch) + fb0;
 #pragma unroll
-      for (int f = 0; f < kFB; f += 4)
-        *(float4*)(dst + f) = make_float4(acc[f][nt][r], acc[f + 1][nt][r], acc[f + 2][nt][r], acc[f + 3][nt][r]);
+      for (int f = 0; f < FB; f += 4)
+        *(float4*)(dst + f) =
+            make_float4(acc[m][f][nt][r], acc[m][f + 1][nt][r], acc[m][f + 2][nt][r], acc[m][f + 3][nt][r]);
     }
   }
 }
 
 bool phasor_mfma_f32_supported(int n_chunks) { return n_chunks >= 3 && n_chunks <= 24; }
 
-hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st) {
-  if (!phasor_mfma_f32_supported(a.n_chunks)) return hipErrorInvalidValue;
-  const int n_dmt = (a.n_dm + kDmTile - 1) / kDmTile;
-  const int n_bb = (a.n_bins + kFB - 1) / kFB;
+namespace {
+template <int FB, int KC, int MW>
+hipError_t launch_tile(const PhasorArgs& a, hipStream_t st) {
+  const int n_dmt = (a.n_dm + 64 * MW - 1) / (64 * MW);
+  const int n_bb = (a.n_bins + FB - 1) / FB;
   const int n_bb8 = (n_bb + kXcds - 1) / kXcds * kXcds;
   const int64_t blocks = (int64_t)n_dmt * n_bb8;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const int nt = (2 * a.n_chunks + 15) / 16;
-  switch (nt) {
-    case 1: hipLaunchKernelGGL((k_phasor_mfma_f32<1>), dim3((unsigned)blocks), dim3(256), 0, st, a, n_dmt, n_bb); break;
-    case 2: hipLaunchKernelGGL((k_phasor_mfma_f32<2>), dim3((unsigned)blocks), dim3(256), 0, st, a, n_dmt, n_bb); break;
-    case 3: hipLaunchKernelGGL((k_phasor_mfma_f32<3>), dim3((unsigned)blocks), dim3(256), 0, st, a, n_dmt, n_bb); break;
+  const dim3 grid((unsigned)blocks), block(256);
+  switch ((2 * a.n_chunks + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_phasor_mfma_f32<1, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 2: hipLaunchKernelGGL((k_phasor_mfma_f32<2, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 3: hipLaunchKernelGGL((k_phasor_mfma_f32<3, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+}  // namespace
+
+// Tile variants (tuning): bins per workgroup x channels per LDS stage x DM sub-tiles per wave.
+hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st) {
+  if (!phasor_mfma_f32_supported(a.n_chunks)) return hipErrorInvalidValue;
+  switch (a.tile_variant) {
+    case 1: return launch_tile<16, 8, 1>(a, st);
+    case 2: return launch_tile<8, 16, 1>(a, st);
+    case 3: return launch_tile<4, 8, 2>(a, st);
+    case 4: return launch_tile<4, 16, 2>(a, st);
+    default: return launch_tile<8, 8, 1>(a, st);
+  }
 }
 
 }  // namespace fdd

@@ -7,7 +7,9 @@
 // host synchronisation, the stages of Algorithm 1: transpose/unpack (8-bit input only),
 // forward FFT per channel and chunk, phasor sum, and either the inverse FFT with scaling and
 // discard, or power spectra.
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -204,6 +206,11 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     return fail(FDD_E_UNSUPPORTED, "grid dimension limit exceeded");
   }
   p->kernel = (d.precision == FDD_FP32 && phasor_mfma_f32_supported((int)p->n_chunks)) ? "mfma_f32" : "valu";
+  // tuning override of the matrix-core tile shape
+  if (const char* tv = std::getenv("FDD_TILE_VARIANT")) {
+    const int v = std::atoi(tv);
+    if (v >= 0 && v <= 4) p->tile_variant = v;
+  }
   if (d.precision != FDD_FP32) {
     delete p;
     return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums are not built yet");
@@ -281,30 +288,49 @@ fdd_status fdd_destroy(fdd_plan_t p) {
   return FDD_OK;
 }
 
-fdd_status fdd_profile_enable(fdd_plan_t p, int32_t enable) {
-  if (p == nullptr) return fail(FDD_E_INVALID, "null plan");
+fdd_status fdd_profile_enable(fdd_plan_t p, int32_t depth) {
+  if (p == nullptr || depth < 0) return fail(FDD_E_INVALID, "null plan or negative depth");
   if (p->dry_run) return fail(FDD_E_INVALID, "dry-run plan");
-  if (enable && p->ev[0] == nullptr) {
-    for (auto& e : p->ev) {
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+  for (auto& e : p->ev)
+    if (e != nullptr) (void)hipEventDestroy(e);
+  p->ev.assign((size_t)depth * 5, nullptr);
+  p->ev_ok.assign((size_t)depth * 5, 0);
+  for (auto& e : p->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      p->prof_depth = 0;
+      return hip_fail(r, "hipEventCreate");
     }
   }
-  p->profile = enable != 0;
+  p->prof_depth = depth;
+  p->prof_calls = 0;
   return FDD_OK;
 }
 
-fdd_status fdd_profile_read(fdd_plan_t p, float ms[4]) {
+fdd_status fdd_profile_read(fdd_plan_t p, float ms[4], int32_t* n_calls) {
   if (p == nullptr || ms == nullptr) return fail(FDD_E_INVALID, "null plan or output");
   for (int i = 0; i < 4; ++i) ms[i] = 0.0f;
-  if (!p->profile) return fail(FDD_E_INVALID, "profiling is not enabled");
-  for (int i = 0; i < 4; ++i) {
-    if (!p->ev_recorded[i] || !p->ev_recorded[i + 1]) continue;
-    hipError_t r = hipEventSynchronize(p->ev[i + 1]);
-    if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
-    r = hipEventElapsedTime(&ms[i], p->ev[i], p->ev[i + 1]);
-    if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+  if (n_calls != nullptr) *n_calls = 0;
+  if (p->prof_depth == 0) return fail(FDD_E_INVALID, "profiling is not enabled");
+  const int64_t n = p->prof_calls < p->prof_depth ? p->prof_calls : p->prof_depth;
+  double acc[4] = {0, 0, 0, 0};
+  for (int64_t c = 0; c < n; ++c) {
+    hipEvent_t* e = &p->ev[(size_t)c * 5];
+    const char* ok = &p->ev_ok[(size_t)c * 5];
+    for (int i = 0; i < 4; ++i) {
+      if (!ok[i] || !ok[i + 1]) continue;
+      hipError_t r = hipEventSynchronize(e[i + 1]);
+      if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+      float t = 0.0f;
+      r = hipEventElapsedTime(&t, e[i], e[i + 1]);
+      if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+      acc[i] += t;
+    }
   }
+  for (int i = 0; i < 4; ++i) ms[i] = n > 0 ? (float)(acc[i] / (double)n) : 0.0f;
+  if (n_calls != nullptr) *n_calls = (int32_t)n;
+  p->prof_calls = 0;
+  std::fill(p->ev_ok.begin(), p->ev_ok.end(), 0);
   return FDD_OK;
 }
 
