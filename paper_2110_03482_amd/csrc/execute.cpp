@@ -41,6 +41,7 @@ fdd_status forward(fdd_plan_t p, const void* in, hipStream_t st) {
   f.pitch = p->pitch;
   f.n_chunks = (int)p->n_chunks;
   f.n_rows = d.n_chan;
+  if (d.precision != FDD_FP32) f.l1max = (unsigned int*)(p->d_ws + p->ws.scale);
   hipError_t e = launch_r2c(p->log_len - 1, f, st);
   if (e != hipSuccess) return hip_fail(e, "forward FFT launch");
   mark(p, 2, st);
@@ -52,7 +53,7 @@ PhasorArgs phasor_args(fdd_plan_t p) {
   a.X = (const float2*)(p->d_ws + p->ws.X);
   a.dms = (const double*)(p->d_ws + p->ws.dms);
   a.kappa = (const double*)(p->d_ws + p->ws.kappa);
-  a.col_scale = (const float*)(p->d_ws + p->ws.scale);
+  a.l1max = (const unsigned int*)(p->d_ws + p->ws.scale);
   a.n_dm = p->desc.n_dm;
   a.n_chan = p->desc.n_chan;
   a.n_chunks = (int)p->n_chunks;
@@ -79,7 +80,11 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   PhasorArgs a = phasor_args(p);
   a.Yr = (float*)(p->d_ws + p->ws.Yr);
   a.Yi = (float*)(p->d_ws + p->ws.Yi);
-  hipError_t e = p->kernel == "mfma_f32" ? launch_phasor_mfma_f32(a, st) : launch_phasor_valu(a, st);
+  hipError_t e;
+  if (p->kernel == "mfma_f32") e = launch_phasor_mfma_f32(a, st);
+  else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+  else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+  else e = launch_phasor_valu(a, st);
   if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
   mark(p, 3, st);
   FftArgs f;
@@ -114,7 +119,10 @@ fdd_status fdd_power_spectrum(fdd_plan_t p, const void* in, float* out, void* st
   // transform; the removed offset sits in bin 0 only, with phasor 1
   if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
     a.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
-  hipError_t e = launch_phasor_valu(a, st);
+  hipError_t e;
+  if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+  else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+  else e = launch_phasor_valu(a, st);
   if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
   mark(p, 3, st);
   mark(p, 4, st);

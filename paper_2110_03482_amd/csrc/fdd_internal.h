@@ -26,6 +26,7 @@ struct FftArgs {
   int n_chunks = 0;
   int n_rows = 0;                   // channels (forward) or DMs (inverse)
   float add_full = 0.0f;            // constant restored in chunks wholly inside the data
+  unsigned int* l1max = nullptr;    // forward: per-chunk max L1 norm (float bits), or null
 };
 
 struct PhasorArgs {
@@ -35,7 +36,7 @@ struct PhasorArgs {
   float* P = nullptr;               // [n_dm][n_pow_bins] power spectra, or null
   const double* dms = nullptr;      // [n_dm]
   const double* kappa = nullptr;    // [n_chan] delay in samples per unit DM
-  const float* col_scale = nullptr; // [n_chunks] power-of-two data scales (split precision)
+  const unsigned int* l1max = nullptr; // [n_chunks] max over channels of the series L1 norm (float bits)
   int n_dm = 0;
   int n_chan = 0;
   int n_chunks = 0;
@@ -53,7 +54,9 @@ hipError_t launch_r2c(int log_n, const FftArgs& a, hipStream_t st);
 hipError_t launch_c2r(int log_n, const FftArgs& a, hipStream_t st);
 hipError_t launch_phasor_valu(const PhasorArgs& a, hipStream_t st);
 hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st);
+hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st);
 bool phasor_mfma_f32_supported(int n_chunks);
+bool phasor_split_supported(int n_chunks);
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct WorkspaceLayout {

@@ -49,13 +49,34 @@ __global__ __launch_bounds__(256) void k_transpose_u8(const uint8_t* __restrict_
 
 // ----------------------------------------------------------------------------- forward
 
+// Sum over the workgroup (any size up to 1024); lds needs blockDim.x / 64 floats.
+__device__ __forceinline__ float block_sum(float v, float* lds) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  float r = 0.0f;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) r += lds[i];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_zero_u32(unsigned int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 template <int LOGN, int LOGE, bool U8>
 __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_r2c(
     const uint8_t* __restrict__ in_u8,   // [n_chan][n_samp] (transposed) or null
     const float* __restrict__ in_f32,    // [n_chan][n_samp] or null
     float2* __restrict__ X,              // [n_chan][n_chunks][pitch]
     const float2* __restrict__ twL,      // exp(-2 pi i j / L), j < L
-    int64_t n_samp, int64_t stride, int64_t pitch, int n_chunks) {
+    int64_t n_samp, int64_t stride, int64_t pitch, int n_chunks,
+    unsigned int* __restrict__ l1max) {  // per chunk: max over channels of sum |x| (float bits), or null
   using F = BlockFft<LOGN, LOGE, false>;
   constexpr int N = F::N, E = F::E, T = F::T;
   constexpr int64_t L = 2 * (int64_t)N;
@@ -82,6 +103,15 @@ __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_r2c(
       v[q].x = s < n_samp ? src[s] : 0.0f;
       v[q].y = s + 1 < n_samp ? src[s + 1] : 0.0f;
     }
+  }
+  if (l1max != nullptr) {
+    // |X[f]| <= sum_t |x[t]|: the series' L1 norm bounds every bin, which sets the
+    // power-of-two data scale of the half-precision phasor sums
+    float s1 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < E; ++q) s1 += fabsf(v[q].x) + fabsf(v[q].y);
+    s1 = block_sum(s1, lds);
+    if (t == 0) atomicMax(l1max + k, __float_as_uint(s1));   // non-negative floats order as uints
   }
   F::run(v, lds);
   float2* dst = X + ((int64_t)c * n_chunks + k) * pitch;
@@ -155,12 +185,15 @@ template <int LOGN>
 hipError_t launch_r2c_n(const FftArgs& a, hipStream_t st) {
   constexpr int LOGE = fft_loge<LOGN>();
   dim3 grid((unsigned)a.n_chunks, (unsigned)a.n_rows);
+  if (a.l1max != nullptr) {
+    hipLaunchKernelGGL(k_zero_u32, dim3((a.n_chunks + 255) / 256), dim3(256), 0, st, a.l1max, a.n_chunks);
+  }
   if (a.in_u8 != nullptr)
     hipLaunchKernelGGL((k_r2c<LOGN, LOGE, true>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a.in_u8, a.in_f32, a.X,
-                       a.twL, a.n_samp, a.stride, a.pitch, a.n_chunks);
+                       a.twL, a.n_samp, a.stride, a.pitch, a.n_chunks, a.l1max);
   else
     hipLaunchKernelGGL((k_r2c<LOGN, LOGE, false>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a.in_u8, a.in_f32, a.X,
-                       a.twL, a.n_samp, a.stride, a.pitch, a.n_chunks);
+                       a.twL, a.n_samp, a.stride, a.pitch, a.n_chunks, a.l1max);
   return hipGetLastError();
 }
 

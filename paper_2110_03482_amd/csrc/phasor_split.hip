@@ -1,0 +1,287 @@
+// Phasor sum on the half-precision matrix cores with split operands (precision form).
+//
+// Same contraction as the FP32 kernel (Eqs. 4 and 7, chunks batched per bin):
+//     [Yr | Yi] = sum_c ( Wr [Xr | Xi] + Wi [-Xi | Xr] )
+// written here as one real GEMM whose contraction index runs over (channel, cos/sin part):
+// A[dm][2c + p] = (Wr, Wi)[p],  B[2c + p][n] = (cos operand, sin operand)[p] of column n.
+// Both operands are split into a half-precision head and tail, v = hi + lo with
+// hi = half(v) and lo = half(v - hi), and the product is accumulated in float32 as
+//     A_hi B_hi + A_hi B_lo + A_lo B_hi      (A_lo B_lo, ~2^-22 relative, is dropped).
+// FP16 has a small range, so every data column (chunk k) carries a power-of-two scale
+// 2^(14 - ceil(log2 L1_k)), where L1_k is the largest L1 norm of chunk k's input series over
+// the channels: |X| <= L1 keeps every scaled value below 2^14.  The scale is exact and is
+// divided out in the epilogue.  BF16 needs no scale but uses it all the same.
+//
+// gfx950 v_mfma_f32_16x16x32_{f16,bf16}: lane l holds A[l % 16][8 (l / 16) .. +7] and
+// B[8 (l / 16) .. +7][l % 16] (8 halves each) and D[4 (l / 16) + r][l % 16] in register r.
+// A lane therefore generates the phasors of one DM and four consecutive channels; the B
+// operand of a (bin, column) row is 16 channels x 2 parts = 32 halves, padded to 40 so that
+// the 16-byte reads of eight consecutive lanes fall in distinct LDS banks.  The data operand
+// of the next 16 channels is prefetched into registers while the current one is in use.
+#include "device_math.h"
+#include "fdd_internal.h"
+
+namespace fdd {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+constexpr int kXcds = 8;
+
+template <bool BF>
+struct HalfOps;
+
+template <>
+struct HalfOps<false> {
+  typedef half8 V8;
+  __device__ static __forceinline__ uint16_t bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+  __device__ static __forceinline__ float value(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+  __device__ static __forceinline__ floatx4 mfma(V8 a, V8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct HalfOps<true> {
+  typedef bf16x8 V8;
+  __device__ static __forceinline__ uint16_t bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+  __device__ static __forceinline__ float value(uint16_t b) { return (float)__builtin_bit_cast(__bf16, b); }
+  __device__ static __forceinline__ floatx4 mfma(V8 a, V8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
+
+// Head/tail split of a pair (a, b): hi = (half(a), half(b)), lo = (half(a - hi_a), half(b - hi_b)),
+// each returned as one 32-bit word (first value in the low half).
+template <bool BF>
+__device__ __forceinline__ void split2(float a, float b, uint32_t* hi, uint32_t* lo) {
+  const float2v x = {a, b};
+  if constexpr (BF) {
+    const bf162v h = __builtin_convertvector(x, bf162v);
+    const float2v hb = __builtin_convertvector(h, float2v);
+    const float2v r = {a - hb[0], b - hb[1]};
+    *hi = __builtin_bit_cast(uint32_t, h);
+    *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf162v));
+  } else {
+    const half2v h = __builtin_convertvector(x, half2v);
+    const float2v hb = __builtin_convertvector(h, float2v);
+    const float2v r = {a - hb[0], b - hb[1]};
+    *hi = __builtin_bit_cast(uint32_t, h);
+    *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, half2v));
+  }
+}
+
+// (x, y) -> (x, -y) and (x, y) -> (y, x) on packed half pairs (exact).
+__device__ __forceinline__ uint32_t neg_second(uint32_t w) { return w ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
+}  // namespace
+
+template <bool BF, int NT, int FB>
+__global__ __launch_bounds__(256) void k_phasor_split(PhasorArgs a, int n_dmt, int n_bb) {
+  using H = HalfOps<BF>;
+  typedef typename H::V8 V8;
+  constexpr int KC = 16;                 // channels per LDS stage = one MFMA contraction step
+  constexpr int NCOL = NT * 16;
+  constexpr int ROWW = 20;               // 32-bit words per (bin, column) row: 16 channels + 4 padding
+  // per-bin stride padded by 8 words: the four 16-lane groups of a staging store (bins f, f+2,
+  // f+4, f+6) then land on alternating bank halves
+  constexpr int BINW = NCOL * ROWW + 8;
+  constexpr int PLANEW = FB * BINW;      // words per plane
+  constexpr int PER = (KC * 8 * NT * (FB / 2) + 255) / 256;   // staged float4 per thread, N <= 8 NT
+  __shared__ uint4 lhi[PLANEW / 4];
+  __shared__ uint4 llo[PLANEW / 4];
+  __shared__ float colscale[32];
+
+  const int bid = blockIdx.x;
+  const int xcd = bid % kXcds;
+  const int slot = bid / kXcds;
+  const int bb = (slot / n_dmt) * kXcds + xcd;
+  const int dmt = slot % n_dmt;
+  if (bb >= n_bb) return;                // uniform per workgroup, before any barrier
+  const int fb0 = bb * FB;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int N = a.n_chunks;
+  const int nel = KC * N * (FB / 2);
+
+  for (int i = tid; i < PLANEW / 4; i += 256) {
+    lhi[i] = make_uint4(0u, 0u, 0u, 0u);
+    llo[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  if (tid < N) {
+    const float l1 = __uint_as_float(a.l1max[tid]);
+    int ex = 0;
+    (void)frexpf(l1, &ex);                // l1 <= 2^ex
+    colscale[tid] = l1 > 0.0f ? ldexpf(1.0f, 14 - ex) : 1.0f;
+  }
+  uint32_t* whi = reinterpret_cast<uint32_t*>(lhi);
+  uint32_t* wlo = reinterpret_cast<uint32_t*>(llo);
+
+  // Staging: element e = (channel cl fastest, bin pair fp, chunk k) is the float4 of bins
+  // (2 fp, 2 fp + 1) of (cb + cl, k); prefetched one stage ahead into registers.
+  float4 pf[PER];
+  auto fetch = [&](int cb) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int cl = e % KC;
+      const int fp = (e / KC) % (FB / 2);
+      const int k = e / (KC * (FB / 2));
+      const int c = cb + cl;
+      pf[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (e < nel && c < a.n_chan) pf[q] = *(const float4*)(a.X + ((int64_t)c * N + k) * a.pitch + fb0 + 2 * fp);
+    }
+  };
+  auto deposit = [&]() {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      if (e >= nel) continue;
+      const int cl = e % KC;
+      const int fp = (e / KC) % (FB / 2);
+      const int k = e / (KC * (FB / 2));
+      const float sk = colscale[k];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        uint32_t h, l;                                    // (Re, Im) of X, scaled and split
+        split2<BF>((b ? pf[q].z : pf[q].x) * sk, (b ? pf[q].w : pf[q].y) * sk, &h, &l);
+        const int f = 2 * fp + b;
+        const int w0 = f * BINW + k * ROWW + cl;          // column k: (Re, -Im)
+        const int w1 = f * BINW + (k + N) * ROWW + cl;    // column k + N: (Im, Re)
+        whi[w0] = neg_second(h);
+        wlo[w0] = neg_second(l);
+        whi[w1] = swap_halves(h);
+        wlo[w1] = swap_halves(l);
+      }
+    }
+  };
+
+  const int dm = dmt * 64 + wave * 16 + (lane & 15);
+  const double dmv = a.dms[dm < a.n_dm ? dm : a.n_dm - 1];
+  const int cq = lane >> 4;
+
+  floatx4 acc[FB][NT];
+#pragma unroll
+  for (int f = 0; f < FB; ++f)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[f][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  __syncthreads();                               // colscale
+  fetch(0);
+  for (int cb = 0; cb < a.n_chan; cb += KC) {
+    __syncthreads();                             // the previous stage's operands are consumed
+    deposit();
+    __syncthreads();
+    if (cb + KC < a.n_chan) fetch(cb + KC);      // in flight while this stage computes
+
+    // phasors of this lane's DM for channels cb + 4 cq .. + 3
+    float2 w[4], st[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int c = cb + 4 * cq + q;
+      if (c >= a.n_chan) c = a.n_chan - 1;       // data staged as zeros
+      const PhaseInc inc = phase_increment(dmv * a.kappa[c], a.log_len, a.mode);
+      float sn, cs;
+      sincos_turn(phase_at(inc, (uint32_t)fb0), &sn, &cs);
+      w[q] = make_float2(cs, sn);
+      sincos_turn(inc.hi, &sn, &cs);
+      st[q] = make_float2(cs, sn);
+    }
+    const int rowbase = (lane & 15) * ROWW + 4 * cq;     // words
+#pragma unroll
+    for (int f = 0; f < FB; ++f) {
+      uint32_t ah[4], al[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        split2<BF>(w[q].x, w[q].y, &ah[q], &al[q]);
+        w[q] = cmul(w[q], st[q]);
+      }
+      const V8 Ahi = __builtin_bit_cast(V8, make_uint4(ah[0], ah[1], ah[2], ah[3]));
+      const V8 Alo = __builtin_bit_cast(V8, make_uint4(al[0], al[1], al[2], al[3]));
+      V8 Bhi[NT], Blo[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int at = (f * BINW + 16 * nt * ROWW + rowbase) / 4;
+        Bhi[nt] = __builtin_bit_cast(V8, lhi[at]);
+        Blo[nt] = __builtin_bit_cast(V8, llo[at]);
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[f][nt] = H::mfma(Ahi, Bhi[nt], acc[f][nt]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[f][nt] = H::mfma(Ahi, Blo[nt], acc[f][nt]);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[f][nt] = H::mfma(Alo, Bhi[nt], acc[f][nt]);
+    }
+  }
+
+  if (a.P != nullptr) {
+    // single chunk: column 0 = Re Y, column 1 = Im Y (lanes j = 0 and 1 of each group)
+    const float inv = 1.0f / colscale[0];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int dmr = dmt * 64 + wave * 16 + 4 * (lane >> 4) + r;
+#pragma unroll
+      for (int f = 0; f < FB; ++f) {
+        const float yr = acc[f][0][r] * inv + ((fb0 + f) == 0 ? a.dc_add : 0.0f);
+        const float yi = __shfl_down(acc[f][0][r], 1, 64) * inv;
+        if ((lane & 15) == 0 && dmr < a.n_dm && fb0 + f < a.n_pow_bins)
+          a.P[(int64_t)dmr * a.n_pow_bins + fb0 + f] = fmaf(yr, yr, yi * yi);
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int n = 16 * nt + (lane & 15);
+    if (n >= 2 * N) continue;
+    const int k = n < N ? n : n - N;
+    const float inv = 1.0f / colscale[k];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int dmr = dmt * 64 + wave * 16 + 4 * (lane >> 4) + r;
+      if (dmr >= a.n_dm) continue;
+      float* dst = (n < N ? a.Yr + ((int64_t)dmr * N + n) * a.pitch
+                          : a.Yi + ((int64_t)dmr * N + (n - N)) * a.pitch) + fb0;
+#pragma unroll
+      for (int f = 0; f < FB; f += 4)
+        *(float4*)(dst + f) = make_float4(acc[f][nt][r] * inv, acc[f + 1][nt][r] * inv, acc[f + 2][nt][r] * inv,
+                                          acc[f + 3][nt][r] * inv);
+    }
+  }
+}
+
+bool phasor_split_supported(int n_chunks) { return n_chunks >= 1 && n_chunks <= 24; }
+
+namespace {
+template <bool BF, int FB>
+hipError_t launch_split_fb(const PhasorArgs& a, hipStream_t st) {
+  const int n_dmt = (a.n_dm + 63) / 64;
+  const int n_bb = (a.n_bins + FB - 1) / FB;
+  const int n_bb8 = (n_bb + kXcds - 1) / kXcds * kXcds;
+  const int64_t blocks = (int64_t)n_dmt * n_bb8;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks), block(256);
+  switch ((2 * a.n_chunks + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_phasor_split<BF, 1, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 2: hipLaunchKernelGGL((k_phasor_split<BF, 2, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 3: hipLaunchKernelGGL((k_phasor_split<BF, 3, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st) {
+  if (!phasor_split_supported(a.n_chunks)) return hipErrorInvalidValue;
+  if (a.P != nullptr && a.n_chunks != 1) return hipErrorInvalidValue;
+  return bf16 ? launch_split_fb<true, 8>(a, st) : launch_split_fb<false, 8>(a, st);
+}
+
+}  // namespace fdd

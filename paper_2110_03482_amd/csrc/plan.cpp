@@ -211,9 +211,12 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     const int v = std::atoi(tv);
     if (v >= 0 && v <= 4) p->tile_variant = v;
   }
-  if (d.precision != FDD_FP32) {
-    delete p;
-    return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums are not built yet");
+  if (d.precision == FDD_FP16_SPLIT || d.precision == FDD_BF16_SPLIT) {
+    if (!phasor_split_supported((int)p->n_chunks)) {
+      delete p;
+      return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums support 1 to 24 chunks");
+    }
+    p->kernel = d.precision == FDD_FP16_SPLIT ? "mfma_f16_split" : "mfma_bf16_split";
   }
   fdd_status st = layout(p);
   if (st != FDD_OK) {

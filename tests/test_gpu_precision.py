@@ -1,0 +1,124 @@
+"""GPU parity of the split-precision phasor sums (FP16 and BF16 head/tail on MFMA, FP32 accumulation).
+
+The error of each form is measured against the FP64 oracle and printed; the asserted bounds sit
+above the measured values with margin and are derived in the design notes:
+ - FP16 split: head + tail carry ~22 significant bits and only the tail x tail product
+   (~2^-22) is dropped, so the path is as accurate as FP32 (bound 1e-5, the FP32 bar);
+ - BF16 split: head + tail carry ~16 bits; the dropped tail x tail product and the bf16
+   rounding of the tails leave ~2^-17 per product (bound 1e-4).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fdd = pytest.importorskip("paper_2110_03482_amd")
+
+BOUND = {"fp16_split": 1e-5, "bf16_split": 1e-4}
+
+
+def rel_err(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.linalg.norm(y - ref, axis=-1) / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+
+
+def run_gpu(w, x, mode, precision, power=False):
+    with fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, overlap=w.overlap,
+                  single_chunk=w.single_chunk, input=w.input_kind, mode=mode, precision=precision) as p:
+        xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        out = p.power_spectrum(xd) if power else p.execute(xd)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), p.kernel
+
+
+@pytest.mark.parametrize("precision", ["fp16_split", "bf16_split"])
+@pytest.mark.parametrize("mode", ["exact", "round"])
+def test_split_small(precision, mode):
+    w = W.small_fp32(0)
+    x = W.gaussian_f32(w.n_chan, w.n_samp, 0)
+    offs = O.nearest_sample(O.delays([30.0], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
+    W.inject_pulse_f32(x, offs, 1000, 5.0, circular=True)
+    y, kernel = run_gpu(w, x, mode, precision)
+    ref = O.fdd(x, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, single_chunk=True, mode=mode)
+    err = rel_err(y, ref)
+    print(f"{precision} {mode} small: kernel={kernel} max rel err {err.max():.3e}, max abs {np.abs(y - ref).max():.3e}")
+    assert err.max() <= BOUND[precision]
+    assert int(np.argmax(y[:, 1000])) == 30
+
+
+@pytest.mark.parametrize("precision", ["fp16_split", "bf16_split"])
+@pytest.mark.parametrize("n_dm", [256, 512, 1024, 2048, 4096, 8192])
+def test_precision_sweep(precision, n_dm):
+    """The small band with n_dm trials DM_j = j 64 / n_dm: error per DM count (sampled rows)."""
+    w = W.precision_sweep(n_dm)
+    x = W.gaussian_f32(w.n_chan, w.n_samp, 0)
+    offs = O.nearest_sample(O.delays([30.0], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
+    W.inject_pulse_f32(x, offs, 1000, 5.0, circular=True)
+    y, _ = run_gpu(w, x, "exact", precision)
+    y32, _ = run_gpu(w, x, "exact", "fp32")
+    rows = list(range(0, n_dm, max(1, n_dm // 48)))
+    ref = O.fdd(x, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, single_chunk=True, mode="exact",
+                rows=rows)
+    err = rel_err(y[rows], ref)
+    err32 = rel_err(y32[rows], ref)
+    print(f"sweep {precision} n_dm={n_dm}: max rel err {err.max():.3e} (fp32 path {err32.max():.3e}), "
+          f"max abs {np.abs(y[rows] - ref).max():.3e}")
+    assert err.max() <= BOUND[precision]
+    # fine grids resolve DM 30 only to within the delay smearing of a few trials
+    assert abs(w.dms[int(np.argmax(y[:, 1000]))] - 30.0) <= 0.25
+
+
+CHUNKED = [
+    (13, 20000, 70, 2048, "f32", 10.0),   # 11 chunks, 2 column tiles
+    (64, 50001, 64, 8192, "u8", 40.0),    # 7 chunks, 8-bit
+    (40, 30000, 100, 4096, "f32", 2.0),   # 8 chunks
+    (32, 30000, 33, 2048, "u8", 8.0),     # 21 chunks, 3 column tiles
+]
+
+
+@pytest.mark.parametrize("case", CHUNKED, ids=[f"{c[0]}ch_{c[1]}s_{c[2]}dm_L{c[3]}_{c[4]}" for c in CHUNKED])
+@pytest.mark.parametrize("precision", ["fp16_split", "bf16_split"])
+def test_split_chunked(case, precision):
+    n_chan, n_samp, n_dm, L, kind, dm_max = case
+    seed = n_chan + n_dm
+    w = W.tiny_random(seed, n_chan, n_samp, n_dm, L, single_chunk=False, input_kind=kind, dm_max=dm_max)
+    x = W.gaussian_u8(n_samp, n_chan, seed) if kind == "u8" else W.gaussian_f32(n_chan, n_samp, seed)
+    for mode in ("exact", "round"):
+        y, kernel = run_gpu(w, x, mode, precision)
+        ref = O.fdd(x, kind, w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, L, mode=mode)
+        err = rel_err(y, ref)
+        print(f"{precision} {mode} {case}: kernel={kernel} max rel err {err.max():.3e}")
+        assert err.max() <= BOUND[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp16_split", "bf16_split"])
+def test_split_power(precision):
+    w = W.small_fp32(3)
+    x = W.gaussian_f32(w.n_chan, w.n_samp, 3)
+    P, _ = run_gpu(w, x, "exact", precision, power=True)
+    tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+    ref = O.oracle_fdd_rows(x, "f32", tau, w.chunk_len, w.chunk_len, 1, True, "exact", power=True)
+    err = rel_err(P, ref)
+    print(f"{precision} power: max rel err {err.max():.3e}")
+    assert err.max() <= 2 * BOUND[precision]
+
+
+def test_split_paper_shaped_rows():
+    w = W.paper_shaped_u8()
+    x = W.gaussian_u8(w.n_samp, w.n_chan, 0)
+    for dm, t0 in ((100.0, 1 << 18), (450.0, 1 << 19), (900.0, 3 << 18)):
+        offs = O.nearest_sample(O.delays([dm], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
+        W.inject_pulse_u8(x, offs, t0, 80.0)
+    y, kernel = run_gpu(w, x, "exact", "fp16_split")
+    rows = [3, 921]
+    ref = O.fdd(x, "u8", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, mode="exact", rows=rows)
+    err = rel_err(y[rows], ref)
+    print(f"fp16_split paper-shaped rows {rows}: kernel={kernel} rel err {err}")
+    assert err.max() <= BOUND["fp16_split"]
+    for trial, t0 in ((205, 1 << 18), (921, 1 << 19), (1842, 3 << 18)):
+        assert abs(int(np.argmax(y[:, t0 - 2: t0 + 3].max(axis=1))) - trial) <= 2
