@@ -73,6 +73,7 @@ typedef enum {
 /* Plan flags. */
 #define FDD_PLAN_DRY_RUN 1u             /* validate and size only; no device calls at all */
 #define FDD_PLAN_EXTERNAL_WORKSPACE 2u  /* caller attaches the workspace with fdd_set_workspace */
+#define FDD_PLAN_POWER_ONLY 4u          /* the plan will only compute power spectra: no inverse buffers */
 
 typedef struct {
   int32_t n_chan;               /* channels, >= 1 */
@@ -82,7 +83,7 @@ typedef struct {
   int32_t n_dm;                 /* trial DMs, >= 1 */
   const double* dm;             /* host array [n_dm], finite, >= 0 (pc cm^-3); copied */
   int64_t n_samp;               /* time samples per channel, >= 1 */
-  int64_t chunk_len;            /* FFT length L: power of two, 2^6 .. 2^16 */
+  int64_t chunk_len;            /* FFT length L: power of two, 2^6 .. 2^22 (above 2^16: multi-pass FFT) */
   int64_t overlap;              /* D = L - S; <= 0 picks ceil(max tau); ignored if single_chunk */
   int32_t single_chunk;         /* 1: one circular transform of length L >= n_samp */
   int32_t input;                /* fdd_input_kind */
@@ -121,7 +122,8 @@ fdd_status fdd_set_workspace(fdd_plan_t plan, void* d_workspace, size_t bytes);
 
 /* Dedisperse: d_in is described by the plan's input kind; d_out is float32 [n_dm][n_samp]
  * (DM-major, Sec. 3).  Enqueued on `stream`; does not synchronise.
- * Errors: FDD_E_INVALID (null pointers, dry-run plan), FDD_E_WORKSPACE, FDD_E_DEVICE. */
+ * Errors: FDD_E_INVALID (null pointers, dry-run plan), FDD_E_UNSUPPORTED (power-only plan),
+ * FDD_E_WORKSPACE, FDD_E_DEVICE. */
 fdd_status fdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
 /* Power spectra without the inverse transform (Sec. 5): d_out is float32 [n_dm][L/2],

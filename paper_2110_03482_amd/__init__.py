@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "FDD_OK", "FDD_IN_U8_TIME_MAJOR", "FDD_IN_F32_CHAN_MAJOR", "FDD_FP32", "FDD_FP16_SPLIT",
     "FDD_BF16_SPLIT", "FDD_DELAY_EXACT", "FDD_DELAY_ROUND", "FDD_PLAN_DRY_RUN",
-    "FDD_PLAN_EXTERNAL_WORKSPACE", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
+    "FDD_PLAN_EXTERNAL_WORKSPACE", "FDD_PLAN_POWER_ONLY", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
     "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
     "fdd_power_spectrum", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
     "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_kernel", "fdd_status_string",
@@ -29,10 +29,11 @@ FDD_OK = 0
 FDD_IN_U8_TIME_MAJOR, FDD_IN_F32_CHAN_MAJOR = 0, 1
 FDD_FP32, FDD_FP16_SPLIT, FDD_BF16_SPLIT = 0, 1, 2
 FDD_DELAY_EXACT, FDD_DELAY_ROUND = 0, 1
-FDD_PLAN_DRY_RUN, FDD_PLAN_EXTERNAL_WORKSPACE = 1, 2
+FDD_PLAN_DRY_RUN, FDD_PLAN_EXTERNAL_WORKSPACE, FDD_PLAN_POWER_ONLY = 1, 2, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-library_path = os.path.join(_HERE, "lib", "libfdd.so")
+# FDD_LIBRARY overrides the in-tree build (e.g. to compare two builds of the library)
+library_path = os.environ.get("FDD_LIBRARY") or os.path.join(_HERE, "lib", "libfdd.so")
 
 
 class FddError(RuntimeError):
@@ -216,7 +217,7 @@ class Plan:
 
     def __init__(self, freqs_mhz, ref_freq_mhz: float, tsamp_s: float, dms, n_samp: int, chunk_len: int,
                  overlap: int = 0, single_chunk: bool = False, input: str = "f32", precision: str = "fp32",
-                 mode: str = "exact", device=None, dry_run: bool = False):
+                 mode: str = "exact", device=None, dry_run: bool = False, power_only: bool = False):
         self._freqs = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
         self._dms = np.ascontiguousarray(dms, dtype=np.float64)
         self.n_chan = int(self._freqs.size)
@@ -238,7 +239,7 @@ class Plan:
         d.input = _INPUTS[input]
         d.precision = _PRECISIONS[precision]
         d.delay_mode = _MODES[mode]
-        d.flags = FDD_PLAN_DRY_RUN if dry_run else FDD_PLAN_EXTERNAL_WORKSPACE
+        d.flags = (FDD_PLAN_DRY_RUN if dry_run else FDD_PLAN_EXTERNAL_WORKSPACE) | (FDD_PLAN_POWER_ONLY if power_only else 0)
         self._handle = fdd_plan(d)
         self.geometry = fdd_plan_info(self._handle)
         self.kernel = fdd_plan_kernel(self._handle)

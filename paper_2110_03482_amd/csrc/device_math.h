@@ -1,5 +1,5 @@
-// Device-side arithmetic shared by the gfx950 kernels: exact phase reduction and sin/cos of a
-// fraction of a turn.
+// Device-side arithmetic shared by the gfx950 kernels: exact phases and sin/cos of a fraction
+// of a turn.
 //
 // Phases are unsigned fixed-point fractions of a turn.  The phasor of Eq. 4 for bin f and
 // delay tau is exp(+2 pi i f tau / L); its phase f*tau/L is only needed modulo one turn.  A
@@ -7,6 +7,11 @@
 // (d mod L) << (64 - log2 L)) gives the phase of bin f as the wrapping product inc * f, whose
 // top 32 bits feed sincos_turn.  This keeps the argument exact however large f*tau becomes;
 // float32 arithmetic on f*tau would lose all phase information at the paper's sizes.
+//
+// The planner tabulates, per (channel, DM), the increment and the unit phasor of one bin step
+// (evaluated in float64 from all 64 bits), channel-major: entry (c, dm) = {inc.lo, inc.hi,
+// cos, sin}.  A kernel seeds a run of bins with one 16-byte load and one sincos_turn, then
+// walks the run by complex multiplication.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,31 +23,6 @@ struct PhaseInc {
   uint32_t hi;  // top 32 bits of the 64-bit turn fraction
   uint32_t lo;  // next 32 bits
 };
-
-// Delay-mode codes (match fdd_delay_mode).
-constexpr int kDelayExact = 0;
-constexpr int kDelayRound = 1;
-
-// Phase increment per Fourier bin for a delay of tau samples and transform length 2^log_len.
-__device__ __forceinline__ PhaseInc phase_increment(double tau, int log_len, int mode) {
-  PhaseInc r;
-  if (mode == kDelayRound) {
-    // nearest sample, halves up; the phase of bin f is (d f mod L) / L exactly
-    double d = floor(tau + 0.5);
-    double dm = d - ldexp(floor(ldexp(d, -log_len)), log_len);   // d mod L, exact
-    r.hi = (uint32_t)dm << (32 - log_len);
-    r.lo = 0u;
-  } else {
-    double v = ldexp(tau, -log_len);        // tau / L, exact
-    double fr = v - floor(v);               // in [0, 1), exact
-    double s = ldexp(fr, 32);               // < 2^32
-    double h = floor(s);
-    double rem = ldexp(s - h, 32);          // < 2^32, exact
-    r.hi = (uint32_t)h;
-    r.lo = (uint32_t)fmin(floor(rem), 4294967295.0);
-  }
-  return r;
-}
 
 // Top 32 bits of (inc * f) mod 2^64, for f < 2^32.
 __device__ __forceinline__ uint32_t phase_at(PhaseInc inc, uint32_t f) {
@@ -71,6 +51,15 @@ __device__ __forceinline__ void sincos_turn(uint32_t p, float* s_out, float* c_o
   const float sn = (qq & 1u) ? c : s;
   *c_out = (qq == 1u || qq == 2u) ? -cs : cs;
   *s_out = (qq >= 2u) ? -sn : sn;
+}
+
+// Phasor of bin f0 and of one bin step, from a table entry {inc.lo, inc.hi, cos, sin}.
+__device__ __forceinline__ void seed_phasor(uint4 e, uint32_t f0, float2* w, float2* step) {
+  const PhaseInc inc = {e.y, e.x};
+  float s, c;
+  sincos_turn(phase_at(inc, f0), &s, &c);
+  *w = make_float2(c, s);
+  *step = make_float2(__uint_as_float(e.z), __uint_as_float(e.w));
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {

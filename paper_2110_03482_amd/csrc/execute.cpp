@@ -42,7 +42,10 @@ fdd_status forward(fdd_plan_t p, const void* in, hipStream_t st) {
   f.n_chunks = (int)p->n_chunks;
   f.n_rows = d.n_chan;
   if (d.precision != FDD_FP32) f.l1max = (unsigned int*)(p->d_ws + p->ws.scale);
-  hipError_t e = launch_r2c(p->log_len - 1, f, st);
+  f.log_n = p->log_len - 1;
+  hipError_t e = f.log_n > kMaxBlockLogN
+                     ? launch_r2c_long(f, (float2*)(p->d_ws + p->ws.Z), (float*)(p->d_ws + p->ws.l1), st)
+                     : launch_r2c(f.log_n, f, st);
   if (e != hipSuccess) return hip_fail(e, "forward FFT launch");
   mark(p, 2, st);
   return FDD_OK;
@@ -51,8 +54,7 @@ fdd_status forward(fdd_plan_t p, const void* in, hipStream_t st) {
 PhasorArgs phasor_args(fdd_plan_t p) {
   PhasorArgs a;
   a.X = (const float2*)(p->d_ws + p->ws.X);
-  a.dms = (const double*)(p->d_ws + p->ws.dms);
-  a.kappa = (const double*)(p->d_ws + p->ws.kappa);
+  a.ptab = (const uint4*)(p->d_ws + p->ws.ptab);
   a.l1max = (const unsigned int*)(p->d_ws + p->ws.scale);
   a.n_dm = p->desc.n_dm;
   a.n_chan = p->desc.n_chan;
@@ -61,7 +63,6 @@ PhasorArgs phasor_args(fdd_plan_t p) {
   a.n_bins = (int)p->n_bins;
   a.n_pow_bins = (int)(p->L / 2);
   a.log_len = p->log_len;
-  a.mode = p->desc.delay_mode;
   a.tile_variant = p->tile_variant;
   return a;
 }
@@ -73,6 +74,7 @@ extern "C" {
 fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   fdd_status s = check_ready(p, in, out);
   if (s != FDD_OK) return s;
+  if (p->desc.flags & FDD_PLAN_POWER_ONLY) return fail(FDD_E_UNSUPPORTED, "the plan was made for power spectra only");
   hipStream_t st = (hipStream_t)stream;
   mark(p, 0, st);
   s = forward(p, in, st);
@@ -99,7 +101,10 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   f.n_chunks = (int)p->n_chunks;
   f.n_rows = p->desc.n_dm;
   f.add_full = p->desc.input == FDD_IN_U8_TIME_MAJOR ? 128.0f * (float)p->desc.n_chan : 0.0f;
-  e = launch_c2r(p->log_len - 1, f, st);
+  f.log_n = p->log_len - 1;
+  e = f.log_n > kMaxBlockLogN
+          ? launch_c2r_long(f, (float2*)(p->d_ws + p->ws.Z), (float2*)(p->d_ws + p->ws.Yr), st)
+          : launch_c2r(f.log_n, f, st);
   if (e != hipSuccess) return hip_fail(e, "inverse FFT launch");
   mark(p, 4, st);
   return FDD_OK;

@@ -27,6 +27,24 @@ struct FftArgs {
   int n_rows = 0;                   // channels (forward) or DMs (inverse)
   float add_full = 0.0f;            // constant restored in chunks wholly inside the data
   unsigned int* l1max = nullptr;    // forward: per-chunk max L1 norm (float bits), or null
+  int log_n = 0;                    // log2 of the complex points per series (L / 2)
+};
+
+// Arguments of the global-memory passes of long transforms.
+struct LongPassArgs {
+  const float2* in = nullptr;
+  float2* out = nullptr;
+  int64_t in_pitch = 0, out_pitch = 0;   // complex points between series
+  const uint8_t* in_u8 = nullptr;        // first forward pass: real input
+  const float* in_f32 = nullptr;
+  float* out_real = nullptr;             // last inverse pass: real output [row][n_samp]
+  const float* yr = nullptr;             // inverse pre-split: Y planes
+  const float* yi = nullptr;
+  float* l1sum = nullptr;                // per-series L1 norm accumulation, or null
+  int log_n = 0, log_ns = 0;
+  int n_series = 0, n_chunks = 1;
+  int64_t stride = 0, n_samp = 0, keep = 0;
+  float add_full = 0.0f;
 };
 
 struct PhasorArgs {
@@ -34,8 +52,7 @@ struct PhasorArgs {
   float* Yr = nullptr;              // [n_dm][n_chunks][pitch] (null for power spectra)
   float* Yi = nullptr;
   float* P = nullptr;               // [n_dm][n_pow_bins] power spectra, or null
-  const double* dms = nullptr;      // [n_dm]
-  const double* kappa = nullptr;    // [n_chan] delay in samples per unit DM
+  const uint4* ptab = nullptr;      // [n_chan][n_dm] {inc.lo, inc.hi, step cos, step sin}
   const unsigned int* l1max = nullptr; // [n_chunks] max over channels of the series L1 norm (float bits)
   int n_dm = 0;
   int n_chan = 0;
@@ -44,14 +61,25 @@ struct PhasorArgs {
   int n_bins = 0;                   // L/2 + 1
   int n_pow_bins = 0;               // L/2
   int log_len = 0;                  // log2 L
-  int mode = 0;                     // fdd_delay_mode
   float dc_add = 0.0f;              // added to Re Y at bin 0 before power (8-bit zero point)
   int tile_variant = 0;             // matrix-core tile shape (0 = default)
 };
 
+// A 1-D sequence of `blocks` workgroups laid out as a 2-D grid whose linear order
+// (y * gridDim.x + x) is the sequence: the work-item count of one grid dimension must stay
+// below 2^32.  Rows are multiples of 8 workgroups, so the linear id modulo 8 is the XCD.
+inline dim3 linear_grid(int64_t blocks) {
+  const int64_t row = int64_t(1) << 16;
+  if (blocks <= row) return dim3((unsigned)blocks);
+  return dim3((unsigned)row, (unsigned)((blocks + row - 1) / row));
+}
+
 hipError_t launch_transpose_u8(const uint8_t* in, uint8_t* out, int64_t n_samp, int n_chan, hipStream_t st);
 hipError_t launch_r2c(int log_n, const FftArgs& a, hipStream_t st);
 hipError_t launch_c2r(int log_n, const FftArgs& a, hipStream_t st);
+hipError_t launch_r2c_long(const FftArgs& a, float2* work, float* l1sum, hipStream_t st);
+hipError_t launch_c2r_long(const FftArgs& a, float2* work, float2* work2, hipStream_t st);
+constexpr int kMaxBlockLogN = 15;   // longest transform held by one workgroup: 2^15 complex points
 hipError_t launch_phasor_valu(const PhasorArgs& a, hipStream_t st);
 hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st);
 hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st);
@@ -61,12 +89,13 @@ bool phasor_split_supported(int n_chunks);
 // Byte offsets of the workspace regions (256-byte aligned).
 struct WorkspaceLayout {
   size_t tw = 0, tw_bytes = 0;        // float2 twiddles, L entries
-  size_t dms = 0, dms_bytes = 0;      // double [n_dm]
-  size_t kappa = 0, kappa_bytes = 0;  // double [n_chan]
+  size_t ptab = 0, ptab_bytes = 0;    // uint4 [n_chan][n_dm] phase increments and step phasors
   size_t scale = 0, scale_bytes = 0;  // float [n_chunks]
   size_t xt = 0, xt_bytes = 0;        // transposed uint8 input
   size_t X = 0, X_bytes = 0;          // float2 [n_chan][n_chunks][pitch]
-  size_t Yr = 0, Yi = 0, Y_bytes = 0; // float planes [n_dm][n_chunks][pitch] each
+  size_t Yr = 0, Yi = 0, Y_bytes = 0; // float planes [n_dm][n_chunks][pitch] each (not for power-only plans)
+  size_t Z = 0, Z_bytes = 0;          // long transforms: float2 [max(n_chan, n_dm) * n_chunks][L/2]
+  size_t l1 = 0, l1_bytes = 0;        // long transforms: per-series L1 sums
   size_t total = 0;
 };
 

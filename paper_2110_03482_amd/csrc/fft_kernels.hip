@@ -173,6 +173,278 @@ __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_c2r(
   }
 }
 
+// ----------------------------------------------------------------------------- long transforms
+//
+// Transforms longer than one workgroup can hold (N = L/2 > 2^15 complex points) run as a
+// sequence of global-memory Stockham passes, one radix-R butterfly per thread: butterfly j of
+// a series reads points j + r N/R (consecutive threads, consecutive addresses), applies the
+// twiddles exp(-/+ 2 pi i r k / (Ns R)), k = j mod Ns, and writes to the autosort positions
+// (j / Ns) Ns R + k + r Ns.  The first forward pass loads real samples directly (packing
+// x[2j] + i x[2j+1], zero point and zero padding as in k_r2c); the last inverse pass stores
+// real samples directly (scaling, valid-sample extraction and zero-point restore as in k_c2r).
+
+enum { kPassComplex = 0, kPassLoadF32 = 1, kPassLoadU8 = 2, kPassStoreReal = 3 };
+
+template <int LOGR, bool INV, int MODE>
+__global__ __launch_bounds__(256) void k_fft_pass(LongPassArgs a) {
+  constexpr int R = 1 << LOGR;
+  const int64_t nb = (int64_t)1 << (a.log_n - LOGR);     // butterflies per series
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= nb) return;
+  const int series = blockIdx.y;                          // (row, chunk) = (series / n_chunks, % n_chunks)
+  const int64_t Ns = (int64_t)1 << a.log_ns;
+  const int64_t k = j & (Ns - 1);
+  float2 v[R];
+  if constexpr (MODE == kPassLoadF32 || MODE == kPassLoadU8) {
+    const int row = series / a.n_chunks, chunk = series % a.n_chunks;
+    const int64_t s0 = (int64_t)chunk * a.stride;
+    const int64_t L = (int64_t)2 << a.log_n;
+    float zp = 0.0f;
+    float l1 = 0.0f;
+    if constexpr (MODE == kPassLoadU8) zp = (s0 + L <= a.n_samp) ? 128.0f : 0.0f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t s = s0 + 2 * (j + r * nb);
+      float x0 = 0.0f, x1 = 0.0f;
+      if constexpr (MODE == kPassLoadU8) {
+        const uint8_t* src = a.in_u8 + (int64_t)row * a.n_samp;
+        if (s < a.n_samp) x0 = (float)src[s] - zp;
+        if (s + 1 < a.n_samp) x1 = (float)src[s + 1] - zp;
+      } else {
+        const float* src = a.in_f32 + (int64_t)row * a.n_samp;
+        if (s < a.n_samp) x0 = src[s];
+        if (s + 1 < a.n_samp) x1 = src[s + 1];
+      }
+      l1 += fabsf(x0) + fabsf(x1);
+      v[r] = make_float2(x0, x1);
+    }
+    if (a.l1sum != nullptr) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) l1 += __shfl_xor(l1, o, 64);
+      if ((threadIdx.x & 63) == 0) atomicAdd(a.l1sum + series, l1);
+    }
+  } else {
+    const float2* src = a.in + (int64_t)series * a.in_pitch;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+  }
+  if (a.log_ns > 0) {
+    // exp(-/+ 2 pi i r k / (Ns R)): angle r k / (Ns R) of a turn, exact in 32-bit fixed point
+    const int sh = 32 - a.log_ns - LOGR;
+    constexpr int G = R > 8 ? 8 : R;
+    float2 lo[G];
+#pragma unroll
+    for (int vv = 1; vv < G; ++vv) lo[vv] = turn_phasor<INV>((uint32_t)(vv * k) << sh);
+#pragma unroll
+    for (int u = 0; u < R / G; ++u) {
+      float2 hi = make_float2(1.0f, 0.0f);
+      if (u > 0) hi = turn_phasor<INV>((uint32_t)(u * G * k) << sh);
+#pragma unroll
+      for (int vv = 0; vv < G; ++vv) {
+        const int r = u * G + vv;
+        if (r == 0) continue;
+        const float2 w = vv == 0 ? hi : (u == 0 ? lo[vv] : cmul(hi, lo[vv]));
+        v[r] = cmul(v[r], w);
+      }
+    }
+  }
+  dft_reg<R, INV>(v);
+  const int64_t base = ((j >> a.log_ns) << (a.log_ns + LOGR)) + k;
+  if constexpr (MODE == kPassStoreReal) {
+    // point m holds samples 2m and 2m + 1 of the chunk
+    const int row = series / a.n_chunks, chunk = series % a.n_chunks;
+    const int64_t s0 = (int64_t)chunk * a.stride;
+    const int64_t L = (int64_t)2 << a.log_n;
+    const float add = (s0 + L <= a.n_samp) ? a.add_full : 0.0f;
+    const int64_t lim = (a.keep < a.n_samp - s0) ? a.keep : a.n_samp - s0;
+    float* dst = a.out_real + (int64_t)row * a.n_samp + s0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t m = base + r * Ns;
+      if (2 * m < lim) dst[2 * m] = v[r].x + add;
+      if (2 * m + 1 < lim) dst[2 * m + 1] = v[r].y + add;
+    }
+  } else {
+    float2* dst = a.out + (int64_t)series * a.out_pitch;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
+// Real-to-complex split of a long series: X[f] for f = 0 .. N from Z[f] and Z[N - f].
+__global__ __launch_bounds__(256) void k_r2c_split(LongPassArgs a) {
+  const int64_t N = (int64_t)1 << a.log_n;
+  const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (f > N) return;
+  const int series = blockIdx.y;
+  const float2* z = a.in + (int64_t)series * a.in_pitch;
+  float2* x = a.out + (int64_t)series * a.out_pitch;
+  const float2 zf = z[f & (N - 1)];
+  const float2 zm = z[(N - f) & (N - 1)];
+  const float2 zc = make_float2(zm.x, -zm.y);
+  const float2 av = make_float2(0.5f * (zf.x + zc.x), 0.5f * (zf.y + zc.y));
+  const float2 d = make_float2(0.5f * (zf.x - zc.x), 0.5f * (zf.y - zc.y));
+  const float2 b = make_float2(d.y, -d.x);                                  // -i d
+  const float2 w = turn_phasor<false>((uint32_t)f << (31 - a.log_n));        // exp(-2 pi i f / L)
+  x[f] = make_float2(av.x + fmaf(w.x, b.x, -w.y * b.y), av.y + fmaf(w.x, b.y, w.y * b.x));
+}
+
+// Complex-to-real pre-split of a long series: Z[f] = A + i B from the planes of Y, scaled 1/N.
+__global__ __launch_bounds__(256) void k_c2r_split(LongPassArgs a) {
+  const int64_t N = (int64_t)1 << a.log_n;
+  const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (f >= N) return;
+  const int series = blockIdx.y;
+  const float* yr = a.yr + (int64_t)series * a.in_pitch;
+  const float* yi = a.yi + (int64_t)series * a.in_pitch;
+  const int64_t fm = N - f;
+  const float2 yf = make_float2(yr[f], f == 0 ? 0.0f : yi[f]);
+  const float2 ym = make_float2(yr[fm], fm == N ? 0.0f : -yi[fm]);       // conj Y[N - f]
+  const float2 av = make_float2(0.5f * (yf.x + ym.x), 0.5f * (yf.y + ym.y));
+  const float2 d = make_float2(0.5f * (yf.x - ym.x), 0.5f * (yf.y - ym.y));
+  const float2 w = turn_phasor<true>((uint32_t)f << (31 - a.log_n));         // exp(+2 pi i f / L)
+  const float2 b = cmul(w, d);
+  const float scale = ldexpf(1.0f, -a.log_n);
+  a.out[(int64_t)series * a.out_pitch + f] = make_float2((av.x - b.y) * scale, (av.y + b.x) * scale);
+}
+
+__global__ void k_l1_max(const float* l1sum, int n_rows, int n_chunks, unsigned int* l1max) {
+  // l1max[k] = max over rows of l1sum[row * n_chunks + k]; one thread per chunk
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_chunks) return;
+  float m = 0.0f;
+  for (int r = 0; r < n_rows; ++r) m = fmaxf(m, l1sum[(int64_t)r * n_chunks + k]);
+  l1max[k] = __float_as_uint(m);
+}
+
+__global__ void k_zero_f32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+namespace {
+constexpr int kLongLogR = 4;
+
+template <bool INV, int MODE>
+hipError_t launch_pass(int logr, LongPassArgs a, hipStream_t st) {
+  const int64_t nb = (int64_t)1 << (a.log_n - logr);
+  const dim3 grid((unsigned)((nb + 255) / 256), (unsigned)a.n_series);
+  switch (logr) {
+    case 1: hipLaunchKernelGGL((k_fft_pass<1, INV, MODE>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_fft_pass<2, INV, MODE>), grid, dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_fft_pass<3, INV, MODE>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_fft_pass<4, INV, MODE>), grid, dim3(256), 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_fft_pass<5, INV, MODE>), grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// radices of the passes: radix 16, the remainder (1..5 bits) folded into the last pass
+void pass_radices(int log_n, int* logr, int* n) {
+  *n = 0;
+  int left = log_n;
+  while (left > 0) {
+    int r = left >= 2 * kLongLogR ? kLongLogR : (left > 5 ? left - kLongLogR : left);
+    logr[(*n)++] = r;
+    left -= r;
+  }
+}
+}  // namespace
+
+// Forward real transform of every (row, chunk) series of length L = 2^(log_n + 1) into
+// X [series][pitch] (bins 0 .. N); `work` holds one series-sized complex buffer per series.
+hipError_t launch_r2c_long(const FftArgs& f, float2* work, float* l1sum, hipStream_t st) {
+  LongPassArgs a;
+  a.log_n = f.log_n;
+  a.n_series = f.n_rows * f.n_chunks;
+  a.n_chunks = f.n_chunks;
+  a.stride = f.stride;
+  a.n_samp = f.n_samp;
+  a.in_u8 = f.in_u8;
+  a.in_f32 = f.in_f32;
+  int logr[16], np = 0;
+  pass_radices(a.log_n, logr, &np);
+  // ping-pong: the last pass must land in `work` so the split can write X
+  float2* bufs[2] = {work, f.X};
+  int cur = (np % 2 == 1) ? 0 : 1;          // buffer receiving pass 0's output
+  hipError_t e = hipSuccess;
+  if (f.l1max != nullptr) {
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((a.n_series + 255) / 256)), dim3(256), 0, st, l1sum,
+                       (int64_t)a.n_series);
+    a.l1sum = l1sum;
+  }
+  int log_ns = 0;
+  for (int p = 0; p < np; ++p) {
+    a.log_ns = log_ns;
+    a.out = bufs[cur];
+    a.out_pitch = cur == 0 ? ((int64_t)1 << a.log_n) : f.pitch;
+    if (p == 0) {
+      e = f.in_u8 != nullptr ? launch_pass<false, kPassLoadU8>(logr[p], a, st)
+                             : launch_pass<false, kPassLoadF32>(logr[p], a, st);
+      a.l1sum = nullptr;
+    } else {
+      e = launch_pass<false, kPassComplex>(logr[p], a, st);
+    }
+    if (e != hipSuccess) return e;
+    a.in = bufs[cur];
+    a.in_pitch = a.out_pitch;
+    cur ^= 1;
+    log_ns += logr[p];
+  }
+  if (f.l1max != nullptr)
+    hipLaunchKernelGGL(k_l1_max, dim3((unsigned)((f.n_chunks + 63) / 64)), dim3(64), 0, st, l1sum, f.n_rows,
+                       f.n_chunks, f.l1max);
+  // final result is in work (pitch N); split into X
+  a.in = work;
+  a.in_pitch = (int64_t)1 << a.log_n;
+  a.out = f.X;
+  a.out_pitch = f.pitch;
+  const int64_t nbins = ((int64_t)1 << a.log_n) + 1;
+  hipLaunchKernelGGL(k_r2c_split, dim3((unsigned)((nbins + 255) / 256), (unsigned)a.n_series), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Inverse real transform of every (DM, chunk) series from the Y planes to the output.
+hipError_t launch_c2r_long(const FftArgs& f, float2* work, float2* work2, hipStream_t st) {
+  LongPassArgs a;
+  a.log_n = f.log_n;
+  a.n_series = f.n_rows * f.n_chunks;
+  a.n_chunks = f.n_chunks;
+  a.stride = f.stride;
+  a.n_samp = f.n_samp;
+  a.keep = f.keep;
+  a.add_full = f.add_full;
+  a.out_real = f.out;
+  a.yr = f.Yr;
+  a.yi = f.Yi;
+  a.in_pitch = f.pitch;
+  a.out = work;
+  a.out_pitch = (int64_t)1 << a.log_n;
+  const int64_t N = (int64_t)1 << a.log_n;
+  hipLaunchKernelGGL(k_c2r_split, dim3((unsigned)((N + 255) / 256), (unsigned)a.n_series), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int logr[16], np = 0;
+  pass_radices(a.log_n, logr, &np);
+  float2* bufs[2] = {work, work2};
+  int cur = 0;
+  int log_ns = 0;
+  for (int p = 0; p < np; ++p) {
+    a.log_ns = log_ns;
+    a.in = bufs[cur];
+    a.in_pitch = N;
+    a.out = bufs[cur ^ 1];
+    a.out_pitch = N;
+    e = (p == np - 1) ? launch_pass<true, kPassStoreReal>(logr[p], a, st)
+                      : launch_pass<true, kPassComplex>(logr[p], a, st);
+    if (e != hipSuccess) return e;
+    cur ^= 1;
+    log_ns += logr[p];
+  }
+  return hipSuccess;
+}
+
 // ----------------------------------------------------------------------------- launchers
 
 namespace {

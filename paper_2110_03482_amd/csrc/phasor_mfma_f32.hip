@@ -13,9 +13,9 @@
 //  - channels stream through LDS in groups of KC = 8: the group's data for the 16 bins is
 //    read from HBM once (128-byte runs along f) and rearranged into the two B planes
 //    [c][f][column] (cos-part and sin-part operands);
-//  - per 4-channel step, lane l generates the phasor of (DM l%16, channel l/16) for the 16
-//    bins: exact 64-bit phase at the first bin and one bin step via sincos_turn, then 15
-//    complex multiplications.  Its cos feeds the first MFMA set and its sin the second, so
+//  - per 4-channel step, lane l generates the phasor of (DM l%16, channel l/16) for the
+//    tile's bins: exact 64-bit phase of the first bin (planner table + sincos_turn), then
+//    complex multiplications by the tabulated step phasor.  Its cos feeds the first MFMA set and its sin the second, so
 //    no phasor is computed twice;
 //  - accumulators live in registers: 16 bins x NT tiles x 4 floats per lane;
 //  - the epilogue writes, per lane, 16 consecutive bins of one (DM, chunk) row of the Yr or
@@ -49,7 +49,8 @@ __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt
   __shared__ float bre[PLANE];
   __shared__ float bim[PLANE];
 
-  const int bid = blockIdx.x;
+  // linear workgroup id; the grid is 2-D only to keep each dimension below 2^32 work-items
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
   const int bb = (slot / n_dmt) * kXcds + xcd;
@@ -109,11 +110,11 @@ __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt
     }
   };
 
-  double dmv[MW];
+  int dmi[MW];
 #pragma unroll
   for (int m = 0; m < MW; ++m) {
     const int dm = dmt * kDmTile + (wave * MW + m) * 16 + (lane & 15);
-    dmv[m] = a.dms[dm < a.n_dm ? dm : a.n_dm - 1];
+    dmi[m] = dm < a.n_dm ? dm : a.n_dm - 1;   // a clamped row's results are not stored
   }
   const int cq = lane >> 4;
 
@@ -136,17 +137,13 @@ __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt
       const int cl = 4 * s + cq;
       int c = cb + cl;
       if (c >= a.n_chan) c = a.n_chan - 1;    // its data were staged as zeros
-      const double kap = a.kappa[c];
+      const uint4* trow = a.ptab + (int64_t)c * a.n_dm;
       const float* pr = bre + cl * CST + (lane & 15);
       const float* pi = bim + cl * CST + (lane & 15);
 #pragma unroll
       for (int m = 0; m < MW; ++m) {
-        const PhaseInc inc = phase_increment(dmv[m] * kap, a.log_len, a.mode);
-        float sn, cs;
-        sincos_turn(phase_at(inc, (uint32_t)fb0), &sn, &cs);
-        float2 w = make_float2(cs, sn);
-        sincos_turn(inc.hi, &sn, &cs);
-        const float2 step = make_float2(cs, sn);
+        float2 w, step;
+        seed_phasor(trow[dmi[m]], (uint32_t)fb0, &w, &step);
         float wr[FB], wi[FB];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
@@ -199,7 +196,7 @@ hipError_t launch_tile(const PhasorArgs& a, hipStream_t st) {
   const int n_bb8 = (n_bb + kXcds - 1) / kXcds * kXcds;
   const int64_t blocks = (int64_t)n_dmt * n_bb8;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)blocks), block(256);
+  const dim3 grid = linear_grid(blocks), block(256);
   switch ((2 * a.n_chunks + 15) / 16) {
     case 1: hipLaunchKernelGGL((k_phasor_mfma_f32<1, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;
     case 2: hipLaunchKernelGGL((k_phasor_mfma_f32<2, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;

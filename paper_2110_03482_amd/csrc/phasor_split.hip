@@ -83,7 +83,7 @@ __device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) |
 }  // namespace
 
 template <bool BF, int NT, int FB>
-__global__ __launch_bounds__(256) void k_phasor_split(PhasorArgs a, int n_dmt, int n_bb) {
+__global__ __launch_bounds__(256, 2) void k_phasor_split(PhasorArgs a, int n_dmt, int n_bb) {
   using H = HalfOps<BF>;
   typedef typename H::V8 V8;
   constexpr int KC = 16;                 // channels per LDS stage = one MFMA contraction step
@@ -98,7 +98,8 @@ __global__ __launch_bounds__(256) void k_phasor_split(PhasorArgs a, int n_dmt, i
   __shared__ uint4 llo[PLANEW / 4];
   __shared__ float colscale[32];
 
-  const int bid = blockIdx.x;
+  // linear workgroup id; the grid is 2-D only to keep each dimension below 2^32 work-items
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
   const int bb = (slot / n_dmt) * kXcds + xcd;
@@ -163,8 +164,8 @@ __global__ __launch_bounds__(256) void k_phasor_split(PhasorArgs a, int n_dmt, i
     }
   };
 
-  const int dm = dmt * 64 + wave * 16 + (lane & 15);
-  const double dmv = a.dms[dm < a.n_dm ? dm : a.n_dm - 1];
+  int dm = dmt * 64 + wave * 16 + (lane & 15);
+  if (dm >= a.n_dm) dm = a.n_dm - 1;             // its results are not stored
   const int cq = lane >> 4;
 
   floatx4 acc[FB][NT];
@@ -187,12 +188,7 @@ __global__ __launch_bounds__(256) void k_phasor_split(PhasorArgs a, int n_dmt, i
     for (int q = 0; q < 4; ++q) {
       int c = cb + 4 * cq + q;
       if (c >= a.n_chan) c = a.n_chan - 1;       // data staged as zeros
-      const PhaseInc inc = phase_increment(dmv * a.kappa[c], a.log_len, a.mode);
-      float sn, cs;
-      sincos_turn(phase_at(inc, (uint32_t)fb0), &sn, &cs);
-      w[q] = make_float2(cs, sn);
-      sincos_turn(inc.hi, &sn, &cs);
-      st[q] = make_float2(cs, sn);
+      seed_phasor(a.ptab[(int64_t)c * a.n_dm + dm], (uint32_t)fb0, &w[q], &st[q]);
     }
     const int rowbase = (lane & 15) * ROWW + 4 * cq;     // words
 #pragma unroll
@@ -267,7 +263,7 @@ hipError_t launch_split_fb(const PhasorArgs& a, hipStream_t st) {
   const int n_bb8 = (n_bb + kXcds - 1) / kXcds * kXcds;
   const int64_t blocks = (int64_t)n_dmt * n_bb8;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)blocks), block(256);
+  const dim3 grid = linear_grid(blocks), block(256);
   switch ((2 * a.n_chunks + 15) / 16) {
     case 1: hipLaunchKernelGGL((k_phasor_split<BF, 1, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;
     case 2: hipLaunchKernelGGL((k_phasor_split<BF, 2, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;

@@ -5,9 +5,9 @@
 // For one spin-frequency bin this is a matrix-vector product per chunk (Sec. 2.3); with a
 // single chunk nothing is shared along the chunk axis, so this kernel is the path for the
 // single-transform workloads, and the fallback for any shape.  Each thread owns one DM and
-// FV consecutive bins.  Per channel it derives the exact 64-bit phase increment of its delay,
-// evaluates the phasor of its first bin and of one bin step with sincos_turn, and walks the
-// remaining bins by complex multiplication (at most FV-1 steps, so the recurrence error stays
+// FV consecutive bins.  Per channel it reads the exact 64-bit phase increment of its delay and
+// the step phasor from the planner's table, evaluates the phasor of its first bin with
+// sincos_turn, and walks the remaining bins by complex multiplication (at most FV-1 steps, so the recurrence error stays
 // at a few float32 ulps).  Threads of a block that share bins read the same data from L1.
 //
 // With P set, the epilogue writes power spectra |Y|^2 for bins below L/2 (Sec. 5) instead of
@@ -30,7 +30,6 @@ __global__ __launch_bounds__(256) void k_phasor_valu(PhasorArgs a) {
   const int dm = blockIdx.y * kDmThreads + ty;
   const int k0 = blockIdx.z * NK;
   if (dm >= a.n_dm || f0 >= a.n_bins) return;   // no barriers in this kernel
-  const double dmv = a.dms[dm];
   float2 acc[NK][FV];
 #pragma unroll
   for (int kk = 0; kk < NK; ++kk)
@@ -40,12 +39,8 @@ __global__ __launch_bounds__(256) void k_phasor_valu(PhasorArgs a) {
   int nk = a.n_chunks - k0;
   if (nk > NK) nk = NK;
   for (int c = 0; c < a.n_chan; ++c) {
-    const PhaseInc inc = phase_increment(dmv * a.kappa[c], a.log_len, a.mode);
-    float s, co;
-    sincos_turn(phase_at(inc, (uint32_t)f0), &s, &co);
-    float2 w = make_float2(co, s);
-    sincos_turn(inc.hi, &s, &co);
-    const float2 step = make_float2(co, s);
+    float2 w, step;
+    seed_phasor(a.ptab[(int64_t)c * a.n_dm + dm], (uint32_t)f0, &w, &step);
     const float2* xr = a.X + ((int64_t)c * a.n_chunks + k0) * a.pitch + f0;
 #pragma unroll
     for (int i = 0; i < FV; ++i) {

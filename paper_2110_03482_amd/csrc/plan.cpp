@@ -50,6 +50,43 @@ static double kappa_of(double f_mhz, double ref_mhz, double tsamp_s) {
   return (FDD_K_DM * (inv_f2 - inv_ref2)) / tsamp_s;
 }
 
+// Per (channel, DM): the 64-bit phase increment per Fourier bin, frac(tau / L) 2^64 (exact
+// (d mod L) << (64 - log2 L) for nearest-sample delays), and the unit phasor of one bin step,
+// exp(+2 pi i inc / 2^64), evaluated in float64.  Channel-major, so that the DM lanes of a
+// kernel read consecutive entries.
+static void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) {
+  const size_t nc = p->kappa.size(), nd = p->dms.size();
+  out->resize(nc * nd);
+  const int lg = p->log_len;
+  for (size_t c = 0; c < nc; ++c) {
+    for (size_t m = 0; m < nd; ++m) {
+      const double tau = p->dms[m] * p->kappa[c];
+      uint32_t hi = 0, lo = 0;
+      if (p->desc.delay_mode == FDD_DELAY_ROUND) {
+        const double d = std::floor(tau + 0.5);
+        const double dl = d - std::ldexp(std::floor(std::ldexp(d, -lg)), lg);   // d mod L, exact
+        hi = (uint32_t)dl << (32 - lg);
+      } else {
+        const double v = std::ldexp(tau, -lg);
+        const double fr = v - std::floor(v);
+        const double s = std::ldexp(fr, 32);
+        const double h = std::floor(s);
+        const double rem = std::ldexp(s - h, 32);
+        hi = (uint32_t)h;
+        lo = (uint32_t)std::min(std::floor(rem), 4294967295.0);
+      }
+      const double ang = 2.0 * M_PI * (std::ldexp((double)hi, -32) + std::ldexp((double)lo, -64));
+      uint4 e;
+      e.x = lo;
+      e.y = hi;
+      float cs = (float)std::cos(ang), sn = (float)std::sin(ang);
+      std::memcpy(&e.z, &cs, 4);
+      std::memcpy(&e.w, &sn, 4);
+      (*out)[c * nd + m] = e;
+    }
+  }
+}
+
 static fdd_status upload_tables(fdd_plan_s* p) {
   const WorkspaceLayout& w = p->ws;
   std::vector<float2> tw((size_t)p->L);
@@ -60,10 +97,10 @@ static fdd_status upload_tables(fdd_plan_s* p) {
   }
   hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), w.tw_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddles)");
-  e = hipMemcpy(p->d_ws + w.dms, p->dms.data(), p->dms.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(dms)");
-  e = hipMemcpy(p->d_ws + w.kappa, p->kappa.data(), p->kappa.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(kappa)");
+  std::vector<uint4> tab;
+  phase_table(p, &tab);
+  e = hipMemcpy(p->d_ws + w.ptab, tab.data(), w.ptab_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase table)");
   return FDD_OK;
 }
 
@@ -77,10 +114,9 @@ static fdd_status layout(fdd_plan_s* p) {
   };
   w.tw_bytes = (size_t)p->L * sizeof(float2);
   put(&w.tw, w.tw_bytes);
-  w.dms_bytes = (size_t)d.n_dm * sizeof(double);
-  put(&w.dms, w.dms_bytes);
-  w.kappa_bytes = (size_t)d.n_chan * sizeof(double);
-  put(&w.kappa, w.kappa_bytes);
+  if (!mul_ok((size_t)d.n_chan * (size_t)d.n_dm, sizeof(uint4), &w.ptab_bytes))
+    return fail(FDD_E_NOMEM, "phase table size overflows");
+  put(&w.ptab, w.ptab_bytes);
   w.scale_bytes = (size_t)p->n_chunks * sizeof(float);
   put(&w.scale, w.scale_bytes);
   if (d.input == FDD_IN_U8_TIME_MAJOR) {
@@ -92,11 +128,24 @@ static fdd_status layout(fdd_plan_s* p) {
       !mul_ok(tmp, sizeof(float2), &w.X_bytes))
     return fail(FDD_E_NOMEM, "Fourier-domain input size overflows");
   put(&w.X, w.X_bytes);
-  if (!mul_ok((size_t)d.n_dm, (size_t)p->n_chunks, &rows) || !mul_ok(rows, (size_t)p->pitch, &tmp) ||
-      !mul_ok(tmp, sizeof(float), &w.Y_bytes))
-    return fail(FDD_E_NOMEM, "Fourier-domain output size overflows");
-  put(&w.Yr, w.Y_bytes);
-  put(&w.Yi, w.Y_bytes);
+  const bool power_only = (d.flags & FDD_PLAN_POWER_ONLY) != 0;
+  if (!power_only) {
+    if (!mul_ok((size_t)d.n_dm, (size_t)p->n_chunks, &rows) || !mul_ok(rows, (size_t)p->pitch, &tmp) ||
+        !mul_ok(tmp, sizeof(float), &w.Y_bytes))
+      return fail(FDD_E_NOMEM, "Fourier-domain output size overflows");
+    put(&w.Yr, w.Y_bytes);
+    put(&w.Yi, w.Y_bytes);
+  }
+  if (p->log_len - 1 > kMaxBlockLogN) {
+    // long transforms: one complex work buffer, sized for the forward (channels) and, unless
+    // power only, the inverse (DMs) series; the inverse's second buffer is the spent Y memory
+    const size_t series = (size_t)(power_only ? d.n_chan : std::max(d.n_chan, d.n_dm)) * (size_t)p->n_chunks;
+    if (!mul_ok(series, (size_t)(p->L / 2) * sizeof(float2), &w.Z_bytes))
+      return fail(FDD_E_NOMEM, "work buffer size overflows");
+    put(&w.Z, w.Z_bytes);
+    w.l1_bytes = (size_t)d.n_chan * (size_t)p->n_chunks * sizeof(float);
+    put(&w.l1, w.l1_bytes);
+  }
   w.total = off;
   return FDD_OK;
 }
@@ -145,7 +194,7 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
   if (d.delay_mode != FDD_DELAY_EXACT && d.delay_mode != FDD_DELAY_ROUND) return fail(FDD_E_INVALID, "bad delay mode");
   const int64_t L = d.chunk_len;
   if (L < 64 || (L & (L - 1)) != 0) return fail(FDD_E_INVALID, "chunk_len must be a power of two >= 64");
-  if (L > (int64_t(1) << 16)) return fail(FDD_E_UNSUPPORTED, "chunk_len above 2^16 is not supported by this build");
+  if (L > (int64_t(1) << 22)) return fail(FDD_E_UNSUPPORTED, "chunk_len above 2^22 is not supported");
   for (int32_t c = 0; c < d.n_chan; ++c) {
     const double f = d.chan_freq_mhz[c];
     if (!(f > 0.0) || !std::isfinite(f)) return fail(FDD_E_INVALID, "channel frequencies must be finite and > 0");

@@ -66,8 +66,9 @@ def test_dry_run_geometry_paper_shaped():
     assert g.bins_padded % 64 == 0 and g.bins_padded >= g.n_bins
     assert g.max_delay == pytest.approx(float(tau.max()), rel=0, abs=0)
     assert g.n_valid == w.n_samp - int(np.ceil(tau.max()))
-    # X (c64) + two Y planes (f32) + transposed input dominate the workspace
-    expect = (w.n_chan * n * g.bins_padded * 8 + 2 * w.n_dm * n * g.bins_padded * 4 + w.n_chan * w.n_samp)
+    # X (c64) + two Y planes (f32) + transposed input + phase table (16 B per channel and DM)
+    expect = (w.n_chan * n * g.bins_padded * 8 + 2 * w.n_dm * n * g.bins_padded * 4 + w.n_chan * w.n_samp
+              + 16 * w.n_chan * w.n_dm)
     assert expect <= g.workspace_bytes < expect + (1 << 24)
     assert p.kernel == "mfma_f32"
     p.close()
@@ -107,7 +108,7 @@ def test_validation_errors():
         fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, 3000, dry_run=True)
     assert e.value.status == 1
     with pytest.raises(fdd.FddError) as e:
-        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, 1 << 17, dry_run=True)
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, 1 << 23, dry_run=True)
     assert e.value.status == 3
     with pytest.raises(fdd.FddError) as e:
         fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, 5000, 4096, single_chunk=True, dry_run=True)
