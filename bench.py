@@ -12,6 +12,14 @@ path; "forms" repeats the measurement with the FP16- and BF16-split phasor sums,
 relative error against the FP64 oracle that the parity tests measure on this workload.  The
 roofline object refers to the phasor-sum kernel, whose duration is the mean over the timed steps
 of HIP events recorded by the library on the execution stream.
+
+Other workloads (--workload):
+  batched      32 uneven beams (256-1024 channels, 2^16-2^20 float32 samples, 512-4096 DMs,
+               L = 2^16), one pulse each, dedispersed by one fdd_batch_execute (grouped launches
+               replayed from one HIP graph, autotuned phasor-sum kernels); value = sum over
+               beams of N_DM * N_t per second.
+  periodicity  512 channels, one 2^22-sample float32 transform with a 33 ms pulsar at DM 57,
+               4096 DMs 0-500, power spectra [4096][2^21] (fdd_power_spectrum, no inverse FFT).
 """
 from __future__ import annotations
 
@@ -97,6 +105,122 @@ def cpu_baseline(w, x, mode: str):
     }
 
 
+def timed_steps(fn, args, label: str) -> float:
+    """Warm up, then time exactly args.steps calls of fn between two device synchronisations."""
+    import torch
+    for i in range(args.warmup):
+        fn()
+        torch.cuda.synchronize()
+        log(f"{label}: warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()              # one GPU, one rank: this is the barrier
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"{label}: timed {args.steps} steps: {ms:.3f} ms/step")
+    return ms
+
+
+def base_result(args, value: float, ms: float, dtype: str, config: dict) -> dict:
+    return {"metric": METRIC, "value": value, "unit": "DM-trial samples/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def run_batched(args, dev) -> int:
+    """Many uneven beams in one batched call per step."""
+    import torch
+
+    import paper_2110_03482_amd as fdd
+    import workloads as W
+
+    beams = W.batched_beams(args.beams, seed=0)
+    xs, shapes = [], []
+    for w, pulse_dm, t0 in beams:
+        x = W.gaussian_f32(w.n_chan, w.n_samp, w.seed)
+        tau = fdd.fdd_dispersion_delays(w.freqs, w.ref_freq_mhz, w.tsamp_s, pulse_dm)
+        W.inject_pulse_f32(x, np.floor(tau + 0.5).astype(np.int64), t0, 5.0, circular=False)
+        xs.append(torch.from_numpy(x).to(dev))
+        shapes.append([w.n_chan, w.n_samp, w.n_dm])
+        del x
+    log(f"batched: {len(beams)} beams generated")
+    samples = sum(w.n_dm * w.n_samp for w, _, _ in beams)
+    outs = [torch.empty((w.n_dm, w.n_samp), dtype=torch.float32, device=dev) for w, _, _ in beams]
+    forms = {}
+    precisions = ["fp32", "fp16_split"] if args.precision == "all" else [args.precision]
+    for prec in precisions:
+        plans = [fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, input="f32",
+                          precision=prec, mode=args.mode, device=dev, workspace=False) for w, _, _ in beams]
+        flops = sum(8.0 * w.n_dm * w.n_chan * p.geometry.n_bins * p.geometry.n_chunks
+                    for (w, _, _), p in zip(beams, plans))
+        batch = fdd.Batch(plans, tune_cache=args.tune_cache)
+        log(f"batched {prec}: {batch.n_waves} memory wave(s), scratch {batch.scratch_bytes / 2**30:.1f} GiB")
+        t_first = time.perf_counter()
+        batch.execute(xs, outs)           # autotune + graph capture
+        torch.cuda.synchronize()
+        log(f"batched {prec}: first call (tuning + capture) {time.perf_counter() - t_first:.1f} s")
+        ms = timed_steps(lambda: batch.execute(xs, outs), args, f"batched {prec}")
+        # detection check: every beam's pulse peaks within a few trials of its DM
+        hits = 0
+        for (w, pulse_dm, t0), y in zip(beams, outs):
+            peak = int(torch.argmax(y[:, t0 - 2:t0 + 3].amax(dim=1)).item())
+            hits += abs(w.dms[peak] - pulse_dm) <= 2.0 * (w.dms[1] - w.dms[0]) + 1.0
+        d = batch.describe()
+        forms[prec] = {"value": samples / (ms * 1e-3), "ms_per_step": ms, "pulses_found": f"{hits}/{len(beams)}",
+                       "phasor_tflops_whole_step": flops / (ms * 1e-3) / 1e12, "waves": d["waves"],
+                       "tuned": {c["key"]: c["choice"] for c in d["classes"]}}
+        batch.close()
+        for p in plans:
+            p.close()
+    main = forms[precisions[0]]
+    config = {"workload": f"batched_{len(beams)}beams_seed0_{args.mode}", "beams": shapes, "chunk_len": 1 << 16,
+              "input": "f32 channel-major", "band_mhz": [1250.0, 1550.0], "tsamp_s": 64e-6,
+              "dm_range": [0.0, 1000.0], "precision": precisions[0]}
+    result = base_result(args, main["value"], main["ms_per_step"],
+                         "f32" if precisions[0] == "fp32" else "f16x2+f32acc", config)
+    result["forms"] = forms
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def run_periodicity(args, dev) -> int:
+    """Power spectra of a long single transform, without the inverse FFT."""
+    import torch
+
+    import paper_2110_03482_amd as fdd
+    import workloads as W
+
+    w = W.periodicity()
+    x = W.gaussian_f32(w.n_chan, w.n_samp, 0)
+    tau57 = fdd.fdd_dispersion_delays(w.freqs, w.ref_freq_mhz, w.tsamp_s, 57.0)
+    W.inject_periodic_f32(x, tau57, 33.0e-3 / w.tsamp_s, 0.03, 0.3)
+    xd = torch.from_numpy(x).to(dev)
+    del x
+    prec = "fp16_split" if args.precision == "all" else args.precision
+    plan = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, single_chunk=True,
+                    input="f32", precision=prec, mode=args.mode, device=dev, power_only=True)
+    out = torch.empty((w.n_dm, w.n_samp // 2), dtype=torch.float32, device=dev)
+    plan.profile(args.steps)
+    ms = timed_steps(lambda: plan.power_spectrum(xd, out), args, f"periodicity {prec}")
+    stage_ms, _ = plan.stage_ms()
+    g = plan.geometry
+    flops = 8.0 * w.n_dm * w.n_chan * (w.n_samp // 2 + 1)
+    achieved = flops / (stage_ms[2] * 1e-3) / 1e12
+    peak = PEAK["fp32_mfma_TFLOPs"] if prec == "fp32" else PEAK["fp16_mfma_TFLOPs"]
+    config = {"workload": w.name + f"_{args.mode}_power", "n_chan": w.n_chan, "n_samp": w.n_samp, "n_dm": w.n_dm,
+              "chunk_len": int(g.chunk_len), "precision": prec, "phasor_kernel": plan.kernel}
+    result = base_result(args, w.n_dm * w.n_samp / (ms * 1e-3), ms, "f32" if prec == "fp32" else "f16x2+f32acc",
+                         config)
+    result["stages_ms"] = {"forward_fft": stage_ms[1], "phasor_sum_power": stage_ms[2]}
+    result["roofline"] = {"kernel": f"phasor_sum_{plan.kernel}", "bound": "mfma" if plan.kernel.startswith("mfma") else "alu",
+                          "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                          "traffic": None, "algorithmic_flops_per_launch": flops}
+    plan.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +233,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "periodicity"])
+    ap.add_argument("--beams", type=int, default=32, help="batched workload: number of beams")
+    ap.add_argument("--tune-cache", default=None, help="batched workload: autotune cache file")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -136,6 +263,10 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n}), flush=True)
         return 0
+    if args.workload == "batched":
+        return run_batched(args, dev)
+    if args.workload == "periodicity":
+        return run_periodicity(args, dev)
     w = W.paper_shaped_u8(0, n_dm=args.n_dm)
     x = make_paper_input(w, fdd)
     xd = torch.from_numpy(x).to(dev)

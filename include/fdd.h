@@ -142,6 +142,63 @@ fdd_status fdd_destroy(fdd_plan_t plan);
 fdd_status fdd_profile_enable(fdd_plan_t plan, int32_t depth);
 fdd_status fdd_profile_read(fdd_plan_t plan, float ms[4], int32_t* n_calls);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched form: many beams (one plan each, of uneven n_chan / n_samp / n_dm) dedispersed
+ * together.  Sec. 3 processes channels and DMs in batches sized to the device memory; Sec. 5
+ * proposes autotuning such parameters to the data size and names beams observed at once as
+ * work to be processed together.  Here every stage (transpose, forward FFT, phasor sum, inverse FFT) is one
+ * grouped kernel launch over all beams of a memory wave, the whole sequence is captured once
+ * into a HIP graph and replayed by one graph launch per call, and the phasor-sum kernel of
+ * each shape class (precision, FFT length, chunk-column tiles) is chosen by an autotuner that
+ * times every candidate tile shape and launch style on the first call.
+ *
+ * Ownership: the batch owns its tables, Fourier-domain scratch, descriptors, graph and tuning
+ * results; it reads its plans' parameters at create time and never uses their workspaces
+ * (create the plans with FDD_PLAN_EXTERNAL_WORKSPACE to spare the memory).  The plans must
+ * stay alive while the batch exists.  Beams whose scratch (Fourier-domain input and output)
+ * does not fit `scratch_limit` together run in successive waves that reuse one arena.
+ * Results equal fdd_execute of each plan to float32 rounding; with FDD_BATCH_NO_AUTOTUNE the
+ * batch uses the kernels fdd_execute would use and the results are bitwise identical.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct fdd_batch_s* fdd_batch_t;
+
+#define FDD_BATCH_NO_GRAPH 1u     /* enqueue the grouped launches directly (no graph capture) */
+#define FDD_BATCH_NO_AUTOTUNE 2u  /* use the single-plan kernel choice for every class */
+
+typedef struct {
+  uint32_t flags;          /* FDD_BATCH_* */
+  int32_t reserved;        /* must be 0 */
+  size_t scratch_limit;    /* bytes of Fourier-domain scratch; 0 = 3/4 of the free device memory */
+  const char* tune_cache;  /* path of a JSON autotune cache (read at create, rewritten after
+                              tuning), or NULL for an in-process cache only */
+} fdd_batch_desc;
+
+/* Group `n_plans` plans (host array) into a batch on the current device: validates that every
+ * plan can run batched (not dry-run, not power-only, chunk_len <= 2^16), plans the waves,
+ * allocates the scratch, uploads the tables.
+ * Errors: FDD_E_INVALID, FDD_E_UNSUPPORTED, FDD_E_NOMEM, FDD_E_DEVICE. */
+fdd_status fdd_batch_create(int32_t n_plans, const fdd_plan_t* plans, const fdd_batch_desc* desc,
+                            fdd_batch_t* out);
+
+/* Dedisperse every beam: d_in[i] / d_out[i] (host arrays of device pointers) are beam i's
+ * input and float32 [n_dm][n_samp] output, as for fdd_execute.  The first call (and a call
+ * whose pointers differ from the previous call's) synchronises `stream`: it runs the
+ * autotuner if needed, writes the launch descriptors and captures the graph.  Other calls
+ * enqueue one graph launch and do not synchronise.  Calls on one batch must not overlap.
+ * Errors: FDD_E_INVALID, FDD_E_DEVICE. */
+fdd_status fdd_batch_execute(fdd_batch_t batch, const void* const* d_in, float* const* d_out, void* stream);
+
+/* Sizes: memory waves, scratch bytes, table bytes (any output may be NULL). */
+fdd_status fdd_batch_info(fdd_batch_t batch, int32_t* n_waves, size_t* scratch_bytes, size_t* table_bytes);
+
+/* JSON description of the waves, shape classes, tuning candidates (with measured ms) and the
+ * chosen kernels, written NUL-terminated into buf[len]; *needed (may be NULL) receives the
+ * size required.  FDD_E_INVALID if len is too small. */
+fdd_status fdd_batch_describe(fdd_batch_t batch, char* buf, size_t len, size_t* needed);
+
+/* Release the batch (not its plans). */
+fdd_status fdd_batch_destroy(fdd_batch_t batch);
+
 /* Host helpers. */
 /* tau (samples) of every channel at one DM, Eq. 1, exactly as plans compute it. */
 fdd_status fdd_dispersion_delays(int32_t n_chan, const double* chan_freq_mhz, double ref_freq_mhz,

@@ -22,7 +22,8 @@ __all__ = [
     "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
     "fdd_power_spectrum", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
     "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_kernel", "fdd_status_string",
-    "fdd_last_error", "fdd_version", "Plan",
+    "fdd_last_error", "fdd_version", "Plan", "FDD_BATCH_NO_GRAPH", "FDD_BATCH_NO_AUTOTUNE", "BatchDesc",
+    "fdd_batch_create", "fdd_batch_execute", "fdd_batch_info", "fdd_batch_describe", "fdd_batch_destroy", "Batch",
 ]
 
 FDD_OK = 0
@@ -30,6 +31,7 @@ FDD_IN_U8_TIME_MAJOR, FDD_IN_F32_CHAN_MAJOR = 0, 1
 FDD_FP32, FDD_FP16_SPLIT, FDD_BF16_SPLIT = 0, 1, 2
 FDD_DELAY_EXACT, FDD_DELAY_ROUND = 0, 1
 FDD_PLAN_DRY_RUN, FDD_PLAN_EXTERNAL_WORKSPACE, FDD_PLAN_POWER_ONLY = 1, 2, 4
+FDD_BATCH_NO_GRAPH, FDD_BATCH_NO_AUTOTUNE = 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # FDD_LIBRARY overrides the in-tree build (e.g. to compare two builds of the library)
@@ -78,6 +80,15 @@ class PlanGeometry(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class BatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+        ("scratch_limit", ctypes.c_size_t),
+        ("tune_cache", ctypes.c_char_p),
+    ]
+
+
 _lib = None
 
 _SIGNATURES = {
@@ -97,6 +108,15 @@ _SIGNATURES = {
     "fdd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "fdd_last_error": (ctypes.c_char_p, []),
     "fdd_version": (ctypes.c_char_p, []),
+    "fdd_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(BatchDesc),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "fdd_batch_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p]),
+    "fdd_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "fdd_batch_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "fdd_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 
@@ -202,6 +222,38 @@ def fdd_plan_kernel(plan) -> str:
     return library().fdd_plan_kernel(plan).decode()
 
 
+def fdd_batch_create(plans: Sequence, desc: BatchDesc) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(plans))(*[ctypes.c_void_p(p) if isinstance(p, int) else p for p in plans])
+    out = ctypes.c_void_p()
+    _check(library().fdd_batch_create(len(plans), arr, ctypes.byref(desc), ctypes.byref(out)), "fdd_batch_create")
+    return out
+
+
+def fdd_batch_execute(batch, d_in: Sequence[int], d_out: Sequence[int], stream: int = 0) -> None:
+    ins = (ctypes.c_void_p * len(d_in))(*d_in)
+    outs = (ctypes.c_void_p * len(d_out))(*d_out)
+    _check(library().fdd_batch_execute(batch, ins, outs, ctypes.c_void_p(stream)), "fdd_batch_execute")
+
+
+def fdd_batch_info(batch):
+    w, sb, tb = ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(library().fdd_batch_info(batch, ctypes.byref(w), ctypes.byref(sb), ctypes.byref(tb)), "fdd_batch_info")
+    return int(w.value), int(sb.value), int(tb.value)
+
+
+def fdd_batch_describe(batch) -> dict:
+    import json
+    need = ctypes.c_size_t()
+    library().fdd_batch_describe(batch, None, 0, ctypes.byref(need))
+    buf = ctypes.create_string_buffer(int(need.value))
+    _check(library().fdd_batch_describe(batch, buf, int(need.value), None), "fdd_batch_describe")
+    return json.loads(buf.value.decode())
+
+
+def fdd_batch_destroy(batch) -> None:
+    _check(library().fdd_batch_destroy(batch), "fdd_batch_destroy")
+
+
 # ----------------------------------------------------------------------------- tensor wrapper
 
 _PRECISIONS = {"fp32": FDD_FP32, "fp16_split": FDD_FP16_SPLIT, "bf16_split": FDD_BF16_SPLIT}
@@ -217,7 +269,8 @@ class Plan:
 
     def __init__(self, freqs_mhz, ref_freq_mhz: float, tsamp_s: float, dms, n_samp: int, chunk_len: int,
                  overlap: int = 0, single_chunk: bool = False, input: str = "f32", precision: str = "fp32",
-                 mode: str = "exact", device=None, dry_run: bool = False, power_only: bool = False):
+                 mode: str = "exact", device=None, dry_run: bool = False, power_only: bool = False,
+                 workspace: bool = True):
         self._freqs = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
         self._dms = np.ascontiguousarray(dms, dtype=np.float64)
         self.n_chan = int(self._freqs.size)
@@ -252,8 +305,9 @@ class Plan:
                 self._handle = None
                 raise RuntimeError("no GPU visible: the FDD library has no CPU path")
             self.device = torch.device("cuda") if device is None else torch.device(device)
-            self.workspace = torch.empty(int(self.geometry.workspace_bytes), dtype=torch.uint8, device=self.device)
-            fdd_set_workspace(self._handle, self.workspace.data_ptr(), self.workspace.numel())
+            if workspace:   # without one the plan only describes a beam of a Batch
+                self.workspace = torch.empty(int(self.geometry.workspace_bytes), dtype=torch.uint8, device=self.device)
+                fdd_set_workspace(self._handle, self.workspace.data_ptr(), self.workspace.numel())
 
     # -- helpers
     @property
@@ -269,7 +323,7 @@ class Plan:
             want = (torch.uint8, (self.n_samp, self.n_chan))
         else:
             want = (torch.float32, (self.n_chan, self.n_samp))
-        if x.dtype != want[0] or tuple(x.shape) != want[1] or not x.is_contiguous() or x.device != self.workspace.device:
+        if x.dtype != want[0] or tuple(x.shape) != want[1] or not x.is_contiguous() or x.device.type != "cuda":
             raise ValueError(f"input must be a contiguous {want[0]} tensor of shape {want[1]} on {self.device}")
 
     @staticmethod
@@ -314,6 +368,68 @@ class Plan:
             fdd_destroy(self._handle)
             self._handle = None
         self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many plans (beams) dedispersed together by grouped launches replayed from one HIP graph.
+
+    The plans may be made with workspace=False: the batch owns its own scratch.  The first
+    execute runs the autotuner (unless autotune=False) and captures the graph; later calls
+    with the same tensors replay it.
+    """
+
+    def __init__(self, plans: Sequence[Plan], graph: bool = True, autotune: bool = True, scratch_limit: int = 0,
+                 tune_cache: Optional[str] = None):
+        self.plans = list(plans)
+        d = BatchDesc()
+        d.flags = (0 if graph else FDD_BATCH_NO_GRAPH) | (0 if autotune else FDD_BATCH_NO_AUTOTUNE)
+        d.reserved = 0
+        d.scratch_limit = int(scratch_limit)
+        self._cache = tune_cache.encode() if tune_cache else None
+        d.tune_cache = self._cache
+        self._handle = fdd_batch_create([p.handle for p in self.plans], d)
+        self.n_waves, self.scratch_bytes, self.table_bytes = fdd_batch_info(self._handle)
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def describe(self) -> dict:
+        return fdd_batch_describe(self._handle)
+
+    def execute(self, inputs, outputs=None, stream=None):
+        """Dedisperse every beam; returns the list of float32 [n_dm][n_samp] outputs."""
+        import torch
+        if len(inputs) != len(self.plans):
+            raise ValueError("one input per plan expected")
+        for p, x in zip(self.plans, inputs):
+            p._check_input(x)
+        if outputs is None:
+            outputs = [torch.empty((p.n_dm, p.n_samp), dtype=torch.float32, device=x.device)
+                       for p, x in zip(self.plans, inputs)]
+        for p, y in zip(self.plans, outputs):
+            if y.dtype != torch.float32 or tuple(y.shape) != (p.n_dm, p.n_samp) or not y.is_contiguous():
+                raise ValueError("outputs must be contiguous float32 tensors [n_dm][n_samp]")
+        fdd_batch_execute(self._handle, [x.data_ptr() for x in inputs], [y.data_ptr() for y in outputs],
+                          Plan._stream(stream))
+        return outputs
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None:
+            fdd_batch_destroy(self._handle)
+            self._handle = None
 
     def __del__(self):
         try:

@@ -1,0 +1,735 @@
+// Batched form: many beams (one plan each) dedispersed by grouped kernel launches.
+//
+// Sec. 3 of the paper processes channels and DMs in batches sized to the device memory and
+// Sec. 5 proposes autotuning those parameters and processing beams observed together.  On
+// MI355X one beam rarely fills the chip in every stage (a 256-channel, 2-chunk beam has only
+// 512 forward transforms), so the batch runs each stage once for all beams of a memory wave:
+//
+//   zero counters -> [per wave: transpose (8-bit beams) -> grouped R2C per FFT length ->
+//   grouped phasor sum per shape class -> grouped C2R per FFT length]
+//
+// Grouped kernels find their beam from a prefix sum over per-beam tile counts, so beams of
+// any n_chan / n_samp / n_dm share a launch.  The phasor sum of every shape class (precision,
+// FFT length, chunk-column tiles) has several candidate kernels: the matrix-core tile shapes,
+// one-workgroup-per-tile or persistent launches, and the vector-ALU kernel.  The autotuner
+// times each candidate on the batch's own data on the first call and keeps the fastest, in
+// memory and optionally in a JSON cache file.  The launch sequence is then captured into one
+// HIP graph that every later call replays with a single launch.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <new>
+#include <sstream>
+
+#include "fdd_internal.h"
+
+using namespace fdd;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+enum Kind { kValu = 0, kMfmaF32 = 1, kSplitF16 = 2, kSplitBf16 = 3 };
+
+struct Choice {
+  int kind = kValu;
+  int variant = 0;       // matrix-core tile variant, or the chunks per thread of the VALU kernel
+  bool persist = false;
+  std::string name() const {
+    char buf[64];
+    switch (kind) {
+      case kMfmaF32: std::snprintf(buf, sizeof buf, "mfma_f32/v%d/%s", variant, persist ? "persistent" : "grid"); break;
+      case kSplitF16: std::snprintf(buf, sizeof buf, "mfma_f16_split/%s", persist ? "persistent" : "grid"); break;
+      case kSplitBf16: std::snprintf(buf, sizeof buf, "mfma_bf16_split/%s", persist ? "persistent" : "grid"); break;
+      default: std::snprintf(buf, sizeof buf, "valu/nk%d", variant); break;
+    }
+    return buf;
+  }
+};
+
+struct Beam {
+  fdd_plan_t plan = nullptr;
+  int wave = 0;
+  int cls = 0;              // phasor shape class
+  size_t tab = 0;           // phase table (table arena)
+  size_t tw = 0;            // twiddles (table arena)
+  size_t l1 = 0;            // per-chunk L1 maxima (word index in the small arena), split only
+  size_t xt = 0, X = 0, Yr = 0, Yi = 0;   // offsets in the beam's scratch
+  size_t scratch = 0;                      // base of the beam's scratch in the arena
+  size_t bytes = 0;                        // size of the beam's scratch
+};
+
+struct Class {
+  std::string key;
+  int nt = 1;                 // 16-column tiles of the chunk axis (2 N columns)
+  std::vector<Choice> cands;  // cands[0] is the single-plan choice
+  std::vector<float> ms;      // measured per candidate (< 0: not timed)
+  int choice = 0;
+  bool settled = false;       // tuned, cached, or only one candidate
+};
+
+enum Stage { kTranspose = 0, kR2c = 1, kPhasor = 2, kC2r = 3 };
+
+struct Launch {
+  Stage stage = kR2c;
+  int wave = 0;
+  int log_n = 0;              // FFT stages: log2(L / 2)
+  bool u8 = false;
+  int cls = -1;               // phasor stage
+  std::vector<int> beams;
+  size_t args = 0, prefix = 0;   // descriptor buffer offsets
+  size_t ctr = 0;             // phasor stage: word index of its 8 ticket counters
+  int total = 0;
+};
+
+// Process-wide autotune results, keyed by device architecture and shape class.
+std::mutex g_tune_mu;
+std::map<std::string, std::string> g_tune;
+
+bool load_cache_file(const std::string& path, std::map<std::string, std::string>* out) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  // flat JSON object of string -> string; keys and values hold no quotes or escapes
+  size_t i = 0;
+  auto next_str = [&](std::string* v) {
+    const size_t a = s.find('"', i);
+    if (a == std::string::npos) return false;
+    const size_t b = s.find('"', a + 1);
+    if (b == std::string::npos) return false;
+    *v = s.substr(a + 1, b - a - 1);
+    i = b + 1;
+    return true;
+  };
+  std::string k, v;
+  while (next_str(&k) && next_str(&v)) (*out)[k] = v;
+  return true;
+}
+
+bool save_cache_file(const std::string& path, const std::map<std::string, std::string>& m) {
+  const std::string tmp = path + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return false;
+    f << "{\n";
+    size_t n = 0;
+    for (const auto& kv : m) f << "  \"" << kv.first << "\": \"" << kv.second << "\"" << (++n < m.size() ? ",\n" : "\n");
+    f << "}\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+}  // namespace
+
+struct fdd_batch_s {
+  std::vector<Beam> beams;
+  std::vector<Class> classes;
+  std::vector<Launch> launches;
+  int n_waves = 0;
+  uint32_t flags = 0;
+  std::string cache_path, arch;
+  uint8_t* d_tab = nullptr;
+  size_t tab_bytes = 0;
+  uint8_t* d_scr = nullptr;
+  size_t scr_bytes = 0;
+  unsigned int* d_small = nullptr;   // ticket counters, then L1 maxima; zeroed by every call
+  size_t small_words = 0;
+  uint8_t* d_desc = nullptr;
+  std::vector<uint8_t> h_desc;
+  std::vector<const void*> last_in;
+  std::vector<float*> last_out;
+  bool ready = false;                // descriptors and graph match last_in / last_out
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+};
+
+namespace {
+
+void release(fdd_batch_s* b) {
+  if (b->exec != nullptr) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph != nullptr) (void)hipGraphDestroy(b->graph);
+  if (b->cap != nullptr) (void)hipStreamDestroy(b->cap);
+  for (void* p : {(void*)b->d_tab, (void*)b->d_scr, (void*)b->d_small, (void*)b->d_desc})
+    if (p != nullptr) (void)hipFree(p);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->cap = nullptr;
+}
+
+const Choice& chosen(const fdd_batch_s* b, const Launch& l) {
+  const Class& c = b->classes[(size_t)l.cls];
+  return c.cands[(size_t)c.choice];
+}
+
+// Candidate kernels of the phasor sum for a plan's precision and chunk count.
+Class make_class(const fdd_plan_s* p) {
+  Class c;
+  const int N = (int)p->n_chunks;
+  c.nt = (2 * N + 15) / 16;
+  char key[96];
+  const int prec = p->desc.precision;
+  if (prec == FDD_FP16_SPLIT || prec == FDD_BF16_SPLIT) {
+    const int kind = prec == FDD_FP16_SPLIT ? kSplitF16 : kSplitBf16;
+    std::snprintf(key, sizeof key, "%s/L%lld/nt%d", kind == kSplitF16 ? "f16split" : "bf16split",
+                  (long long)p->L, c.nt);
+    c.cands.push_back({kind, 0, false});
+    c.cands.push_back({kind, 0, true});
+  } else if (N == 1) {
+    std::snprintf(key, sizeof key, "fp32/L%lld/n1", (long long)p->L);
+    c.cands.push_back({kValu, 1, false});
+  } else if (N > 24) {
+    std::snprintf(key, sizeof key, "fp32/L%lld/valu", (long long)p->L);
+    c.cands.push_back({kValu, 4, false});
+  } else {
+    const bool small = !phasor_mfma_f32_supported(N);   // the single plan keeps these on the VALU
+    std::snprintf(key, sizeof key, "fp32/L%lld/%s%d", (long long)p->L, small ? "n" : "nt", small ? N : c.nt);
+    if (small) c.cands.push_back({kValu, 4, false});
+    for (int v = 0; v < kMfmaF32Variants; ++v)
+      for (int per = 0; per < 2; ++per) c.cands.push_back({kMfmaF32, v, per == 1});
+    if (!small) c.cands.push_back({kValu, 4, false});
+  }
+  c.key = key;
+  c.ms.assign(c.cands.size(), -1.0f);
+  c.settled = c.cands.size() == 1;
+  return c;
+}
+
+// Scratch bytes of one beam: transposed 8-bit input, X, and the two Y planes.
+size_t beam_scratch(const fdd_plan_s* p, Beam* bm) {
+  const fdd_plan_desc& d = p->desc;
+  size_t off = 0;
+  bm->xt = off;
+  if (d.input == FDD_IN_U8_TIME_MAJOR) off = align_up(off + (size_t)d.n_chan * (size_t)d.n_samp);
+  bm->X = off;
+  off = align_up(off + (size_t)d.n_chan * (size_t)p->n_chunks * (size_t)p->pitch * sizeof(float2));
+  bm->Yr = off;
+  const size_t yb = (size_t)d.n_dm * (size_t)p->n_chunks * (size_t)p->pitch * sizeof(float);
+  off = align_up(off + yb);
+  bm->Yi = off;
+  off = align_up(off + yb);
+  return off;
+}
+
+// Host copy of the launch descriptors for the given pointers and the current choices.
+fdd_status fill(fdd_batch_s* b, const void* const* in, float* const* out) {
+  std::fill(b->h_desc.begin(), b->h_desc.end(), 0);
+  for (Launch& l : b->launches) {
+    if (l.stage == kTranspose) continue;
+    int64_t acc = 0;
+    int* prefix = (int*)(b->h_desc.data() + l.prefix);
+    for (size_t i = 0; i < l.beams.size(); ++i) {
+      const Beam& bm = b->beams[(size_t)l.beams[i]];
+      const fdd_plan_s* p = bm.plan;
+      const fdd_plan_desc& d = p->desc;
+      uint8_t* scr = b->d_scr + bm.scratch;
+      const bool split = d.precision != FDD_FP32;
+      prefix[i] = (int)acc;
+      int64_t tiles = 0;
+      if (l.stage == kPhasor) {
+        PhasorArgs a;
+        a.X = (const float2*)(scr + bm.X);
+        a.Yr = (float*)(scr + bm.Yr);
+        a.Yi = (float*)(scr + bm.Yi);
+        a.ptab = (const uint4*)(b->d_tab + bm.tab);
+        a.l1max = split ? b->d_small + bm.l1 : nullptr;
+        a.n_dm = d.n_dm;
+        a.n_chan = d.n_chan;
+        a.n_chunks = (int)p->n_chunks;
+        a.pitch = p->pitch;
+        a.n_bins = (int)p->n_bins;
+        a.n_pow_bins = (int)(p->L / 2);
+        a.log_len = p->log_len;
+        const Choice& ch = chosen(b, l);
+        a.tile_variant = ch.kind == kMfmaF32 ? ch.variant : 0;
+        if (ch.kind == kMfmaF32) tiles = phasor_mfma_f32_tiles(&a, ch.variant);
+        else if (ch.kind == kValu) tiles = phasor_valu_tiles(&a, ch.variant);
+        else tiles = phasor_split_tiles(&a);
+        std::memcpy(b->h_desc.data() + l.args + i * sizeof(PhasorArgs), &a, sizeof a);
+      } else {
+        FftArgs f;
+        f.twL = (const float2*)(b->d_tab + bm.tw);
+        f.n_samp = d.n_samp;
+        f.stride = p->S;
+        f.pitch = p->pitch;
+        f.n_chunks = (int)p->n_chunks;
+        f.log_n = p->log_len - 1;
+        if (l.stage == kR2c) {
+          if (d.input == FDD_IN_U8_TIME_MAJOR) f.in_u8 = scr + bm.xt;
+          else f.in_f32 = (const float*)in[l.beams[i]];
+          f.X = (float2*)(scr + bm.X);
+          f.n_rows = d.n_chan;
+          f.l1max = split ? b->d_small + bm.l1 : nullptr;
+        } else {
+          f.Yr = (const float*)(scr + bm.Yr);
+          f.Yi = (const float*)(scr + bm.Yi);
+          f.out = out[l.beams[i]];
+          f.keep = d.single_chunk ? d.n_samp : p->S;
+          f.n_rows = d.n_dm;
+          f.add_full = d.input == FDD_IN_U8_TIME_MAJOR ? 128.0f * (float)d.n_chan : 0.0f;
+        }
+        tiles = fft_grouped_tiles(f);
+        std::memcpy(b->h_desc.data() + l.args + i * sizeof(FftArgs), &f, sizeof f);
+      }
+      acc += tiles;
+      if (acc > std::numeric_limits<int>::max()) return fail(FDD_E_UNSUPPORTED, "too many tiles in one grouped launch");
+    }
+    prefix[l.beams.size()] = (int)acc;
+    l.total = (int)acc;
+  }
+  return FDD_OK;
+}
+
+fdd_status upload(fdd_batch_s* b) {
+  hipError_t e = hipMemcpy(b->d_desc, b->h_desc.data(), b->h_desc.size(), hipMemcpyHostToDevice);
+  return e == hipSuccess ? FDD_OK : hip_fail(e, "hipMemcpy(batch descriptors)");
+}
+
+hipError_t enqueue_launch(fdd_batch_s* b, const Launch& l, const void* const* in, hipStream_t st) {
+  const int n = (int)l.beams.size();
+  switch (l.stage) {
+    case kTranspose: {
+      const Beam& bm = b->beams[(size_t)l.beams[0]];
+      const fdd_plan_desc& d = bm.plan->desc;
+      return launch_transpose_u8((const uint8_t*)in[l.beams[0]], b->d_scr + bm.scratch + bm.xt, d.n_samp, d.n_chan,
+                                 st);
+    }
+    case kR2c:
+    case kC2r: {
+      Group<FftArgs> g;
+      g.beams = (const FftArgs*)(b->d_desc + l.args);
+      g.prefix = (const int*)(b->d_desc + l.prefix);
+      g.n_beams = n;
+      g.total = l.total;
+      return l.stage == kR2c ? launch_r2c_grouped(l.log_n, l.u8, g, st) : launch_c2r_grouped(l.log_n, g, st);
+    }
+    case kPhasor: {
+      Group<PhasorArgs> g;
+      g.beams = (const PhasorArgs*)(b->d_desc + l.args);
+      g.prefix = (const int*)(b->d_desc + l.prefix);
+      g.counters = b->d_small + l.ctr;
+      g.n_beams = n;
+      g.total = l.total;
+      const Choice& ch = chosen(b, l);
+      const int nt = b->classes[(size_t)l.cls].nt;
+      switch (ch.kind) {
+        case kMfmaF32: return launch_phasor_mfma_f32_grouped(nt, ch.variant, ch.persist, g, st);
+        case kSplitF16: return launch_phasor_split_grouped(false, nt, ch.persist, g, st);
+        case kSplitBf16: return launch_phasor_split_grouped(true, nt, ch.persist, g, st);
+        default: return launch_phasor_valu_grouped(ch.variant, g, st);
+      }
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+fdd_status enqueue_all(fdd_batch_s* b, const void* const* in, hipStream_t st) {
+  hipError_t e = launch_zero_u32(b->d_small, (int64_t)b->small_words, st);
+  if (e != hipSuccess) return hip_fail(e, "zero launch");
+  for (const Launch& l : b->launches) {
+    e = enqueue_launch(b, l, in, st);
+    if (e != hipSuccess) return hip_fail(e, "grouped launch");
+  }
+  return FDD_OK;
+}
+
+// Time every candidate of every unsettled class on the beams of the first wave holding it:
+// the wave's forward stages run once, then each candidate runs once to warm up and is timed
+// (the best of three when a run is shorter than 50 ms).  Synchronises the stream.
+fdd_status autotune(fdd_batch_s* b, const void* const* in, float* const* out, hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0 != nullptr) (void)hipEventDestroy(e0);
+    return fail(FDD_E_DEVICE, "hipEventCreate failed");
+  }
+  fdd_status s = FDD_OK;
+  auto check = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && s == FDD_OK) s = hip_fail(e, what);
+    return s == FDD_OK;
+  };
+  for (int w = 0; w < b->n_waves && s == FDD_OK; ++w) {
+    bool needed = false;
+    for (const Launch& l : b->launches)
+      if (l.wave == w && l.stage == kPhasor && !b->classes[(size_t)l.cls].settled) needed = true;
+    if (!needed) continue;
+    s = fill(b, in, out);
+    if (s == FDD_OK) s = upload(b);
+    if (s != FDD_OK) break;
+    if (!check(launch_zero_u32(b->d_small, (int64_t)b->small_words, st), "zero launch")) break;
+    for (const Launch& l : b->launches)
+      if (l.wave == w && (l.stage == kTranspose || l.stage == kR2c))
+        if (!check(enqueue_launch(b, l, in, st), "forward launch")) break;
+    for (Launch& l : b->launches) {
+      if (s != FDD_OK) break;
+      if (l.wave != w || l.stage != kPhasor) continue;
+      Class& c = b->classes[(size_t)l.cls];
+      if (c.settled) continue;
+      for (size_t k = 0; k < c.cands.size() && s == FDD_OK; ++k) {
+        c.choice = (int)k;
+        s = fill(b, in, out);
+        if (s == FDD_OK) s = upload(b);
+        float best = -1.0f;
+        for (int rep = 0; rep < 4 && s == FDD_OK; ++rep) {
+          if (!check(launch_zero_u32(b->d_small + l.ctr, 8, st), "zero launch")) break;
+          if (!check(hipEventRecord(e0, st), "hipEventRecord")) break;
+          if (!check(enqueue_launch(b, l, in, st), "tuning launch")) break;
+          if (!check(hipEventRecord(e1, st), "hipEventRecord")) break;
+          if (!check(hipEventSynchronize(e1), "hipEventSynchronize")) break;
+          float ms = 0.0f;
+          if (!check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) break;
+          if (rep == 0) continue;                          // warm-up
+          if (best < 0.0f || ms < best) best = ms;
+          if (rep == 1 && ms >= 50.0f) break;
+        }
+        c.ms[k] = best;
+      }
+      if (s != FDD_OK) break;
+      int arg = 0;
+      for (size_t k = 1; k < c.cands.size(); ++k)
+        if (c.ms[k] >= 0.0f && (c.ms[(size_t)arg] < 0.0f || c.ms[k] < c.ms[(size_t)arg])) arg = (int)k;
+      c.choice = arg;
+      c.settled = true;
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[b->arch + "|" + c.key] = c.cands[(size_t)arg].name();
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s == FDD_OK && !b->cache_path.empty()) {
+    std::map<std::string, std::string> m;
+    (void)load_cache_file(b->cache_path, &m);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      for (const auto& kv : g_tune) m[kv.first] = kv.second;
+    }
+    if (!save_cache_file(b->cache_path, m)) return fail(FDD_E_INVALID, "cannot write the autotune cache " + b->cache_path);
+  }
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_desc* desc, fdd_batch_t* out) {
+  if (out == nullptr) return fail(FDD_E_INVALID, "null output");
+  *out = nullptr;
+  if (n < 1 || plans == nullptr) return fail(FDD_E_INVALID, "a batch needs at least one plan");
+  fdd_batch_desc dd{};
+  if (desc != nullptr) dd = *desc;
+  if (dd.reserved != 0 || (dd.flags & ~(FDD_BATCH_NO_GRAPH | FDD_BATCH_NO_AUTOTUNE)) != 0)
+    return fail(FDD_E_INVALID, "unknown batch flags or nonzero reserved field");
+  for (int32_t i = 0; i < n; ++i) {
+    const fdd_plan_s* p = plans[i];
+    if (p == nullptr) return fail(FDD_E_INVALID, "null plan in batch");
+    if (p->dry_run) return fail(FDD_E_INVALID, "a dry-run plan cannot be batched");
+    if (p->desc.flags & FDD_PLAN_POWER_ONLY) return fail(FDD_E_UNSUPPORTED, "power-only plans cannot be batched");
+    if (p->log_len - 1 > kMaxBlockLogN) return fail(FDD_E_UNSUPPORTED, "batched beams need chunk_len <= 2^16");
+  }
+  fdd_batch_s* b = new (std::nothrow) fdd_batch_s();
+  if (b == nullptr) return fail(FDD_E_NOMEM, "host allocation failed");
+  b->flags = dd.flags;
+  if (dd.tune_cache != nullptr) b->cache_path = dd.tune_cache;
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    delete b;
+    return fail(FDD_E_DEVICE, "no HIP device");
+  }
+  b->arch = prop.gcnArchName;
+  std::map<std::string, std::string> cached;
+  if (!b->cache_path.empty()) (void)load_cache_file(b->cache_path, &cached);
+
+  // beams, shape classes (tuning state from the process cache or the file)
+  b->beams.resize((size_t)n);
+  std::map<std::string, int> class_of;
+  for (int32_t i = 0; i < n; ++i) {
+    Beam& bm = b->beams[(size_t)i];
+    bm.plan = plans[i];
+    Class c = make_class(bm.plan);
+    auto it = class_of.find(c.key);
+    if (it == class_of.end()) {
+      std::string name;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto t = g_tune.find(b->arch + "|" + c.key);
+        if (t != g_tune.end()) name = t->second;
+      }
+      if (name.empty()) {
+        auto t = cached.find(b->arch + "|" + c.key);
+        if (t != cached.end()) name = t->second;
+      }
+      for (size_t k = 0; k < c.cands.size(); ++k)
+        if (!name.empty() && c.cands[k].name() == name) {
+          c.choice = (int)k;
+          c.settled = true;
+        }
+      if (dd.flags & FDD_BATCH_NO_AUTOTUNE) {
+        c.choice = 0;
+        c.settled = true;
+      }
+      it = class_of.emplace(c.key, (int)b->classes.size()).first;
+      b->classes.push_back(c);
+    }
+    bm.cls = it->second;
+  }
+
+  // table arena: one twiddle table per FFT length, one phase table per beam
+  std::map<int64_t, size_t> tw_of;
+  size_t off = 0;
+  for (Beam& bm : b->beams) {
+    const int64_t L = bm.plan->L;
+    auto it = tw_of.find(L);
+    if (it == tw_of.end()) {
+      it = tw_of.emplace(L, off).first;
+      off = align_up(off + (size_t)L * sizeof(float2));
+    }
+    bm.tw = it->second;
+    bm.tab = off;
+    off = align_up(off + (size_t)bm.plan->desc.n_chan * (size_t)bm.plan->desc.n_dm * sizeof(uint4));
+  }
+  b->tab_bytes = off;
+
+  // memory waves: first-fit decreasing over the beams' scratch sizes
+  std::vector<int> order((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    order[(size_t)i] = i;
+    Beam& bm = b->beams[(size_t)i];
+    bm.bytes = beam_scratch(bm.plan, &bm);
+  }
+  size_t limit = dd.scratch_limit;
+  if (limit == 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      release(b);
+      delete b;
+      return fail(FDD_E_DEVICE, "hipMemGetInfo failed");
+    }
+    limit = free_b / 4 * 3 > b->tab_bytes ? free_b / 4 * 3 - b->tab_bytes : 0;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return b->beams[(size_t)x].bytes > b->beams[(size_t)y].bytes; });
+  std::vector<size_t> fill_of;
+  for (int i : order) {
+    Beam& bm = b->beams[(size_t)i];
+    if (bm.bytes > limit) {
+      delete b;
+      return fail(FDD_E_NOMEM, "one beam's scratch (" + std::to_string(bm.bytes) + " bytes) exceeds the scratch limit");
+    }
+    size_t w = 0;
+    while (w < fill_of.size() && fill_of[w] + bm.bytes > limit) ++w;
+    if (w == fill_of.size()) fill_of.push_back(0);
+    bm.wave = (int)w;
+    bm.scratch = fill_of[w];
+    fill_of[w] += bm.bytes;
+  }
+  b->n_waves = (int)fill_of.size();
+  b->scr_bytes = *std::max_element(fill_of.begin(), fill_of.end());
+
+  // launches, wave by wave; grouped beams ordered by decreasing work per tile (channels)
+  size_t words = 0;
+  for (int w = 0; w < b->n_waves; ++w) {
+    std::vector<int> wb;
+    for (int i : order)
+      if (b->beams[(size_t)i].wave == w) wb.push_back(i);
+    std::stable_sort(wb.begin(), wb.end(), [&](int x, int y) {
+      return b->beams[(size_t)x].plan->desc.n_chan > b->beams[(size_t)y].plan->desc.n_chan;
+    });
+    for (int i : wb)
+      if (b->beams[(size_t)i].plan->desc.input == FDD_IN_U8_TIME_MAJOR) {
+        Launch l;
+        l.stage = kTranspose;
+        l.wave = w;
+        l.beams = {i};
+        b->launches.push_back(l);
+      }
+    auto grouped = [&](Stage stage, auto key_of) {
+      std::map<std::pair<int, int>, std::vector<int>> groups;
+      for (int i : wb) groups[key_of(b->beams[(size_t)i])].push_back(i);
+      for (auto& g : groups) {
+        Launch l;
+        l.stage = stage;
+        l.wave = w;
+        l.beams = g.second;
+        const fdd_plan_s* p = b->beams[(size_t)g.second[0]].plan;
+        l.log_n = p->log_len - 1;
+        l.u8 = p->desc.input == FDD_IN_U8_TIME_MAJOR;
+        if (stage == kPhasor) {
+          l.cls = g.first.first;
+          l.ctr = words;
+          words += 8;
+        }
+        b->launches.push_back(l);
+      }
+    };
+    grouped(kR2c, [](const Beam& bm) {
+      return std::make_pair(bm.plan->log_len, bm.plan->desc.input == FDD_IN_U8_TIME_MAJOR ? 1 : 0);
+    });
+    grouped(kPhasor, [](const Beam& bm) { return std::make_pair(bm.cls, 0); });
+    grouped(kC2r, [](const Beam& bm) { return std::make_pair(bm.plan->log_len, 0); });
+  }
+  for (Beam& bm : b->beams)
+    if (bm.plan->desc.precision != FDD_FP32) {
+      bm.l1 = words;
+      words += (size_t)bm.plan->n_chunks;
+    }
+  b->small_words = words;
+
+  // descriptor buffer
+  size_t doff = 0;
+  for (Launch& l : b->launches) {
+    if (l.stage == kTranspose) continue;
+    const size_t each = l.stage == kPhasor ? sizeof(PhasorArgs) : sizeof(FftArgs);
+    l.args = doff;
+    doff = align_up(doff + each * l.beams.size());
+    l.prefix = doff;
+    doff = align_up(doff + sizeof(int) * (l.beams.size() + 1));
+  }
+  b->h_desc.assign(doff, 0);
+
+  // device memory and tables
+  auto alloc = [&](void** p, size_t bytes, const char* what) {
+    hipError_t e = hipMalloc(p, bytes > 0 ? bytes : kAlign);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FDD_E_NOMEM, std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
+    }
+    return FDD_OK;
+  };
+  fdd_status s = alloc((void**)&b->d_tab, b->tab_bytes, "batch tables");
+  if (s == FDD_OK) s = alloc((void**)&b->d_scr, b->scr_bytes, "batch scratch");
+  if (s == FDD_OK) s = alloc((void**)&b->d_small, b->small_words * sizeof(unsigned int), "batch counters");
+  if (s == FDD_OK) s = alloc((void**)&b->d_desc, b->h_desc.size(), "batch descriptors");
+  if (s == FDD_OK) {
+    std::vector<uint8_t> tabs(b->tab_bytes, 0);
+    for (const auto& kv : tw_of) {
+      std::vector<float2> tw;
+      twiddle_table(kv.first, &tw);
+      std::memcpy(tabs.data() + kv.second, tw.data(), tw.size() * sizeof(float2));
+    }
+    for (const Beam& bm : b->beams) {
+      std::vector<uint4> tab;
+      phase_table(bm.plan, &tab);
+      std::memcpy(tabs.data() + bm.tab, tab.data(), tab.size() * sizeof(uint4));
+    }
+    hipError_t e = hipMemcpy(b->d_tab, tabs.data(), b->tab_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) s = hip_fail(e, "hipMemcpy(batch tables)");
+  }
+  if (s == FDD_OK && !(b->flags & FDD_BATCH_NO_GRAPH)) {
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) s = hip_fail(e, "hipStreamCreate");
+  }
+  if (s != FDD_OK) {
+    release(b);
+    delete b;
+    return s;
+  }
+  *out = b;
+  return FDD_OK;
+}
+
+fdd_status fdd_batch_execute(fdd_batch_t b, const void* const* in, float* const* out, void* stream) {
+  if (b == nullptr || in == nullptr || out == nullptr) return fail(FDD_E_INVALID, "null batch, inputs or outputs");
+  const size_t n = b->beams.size();
+  for (size_t i = 0; i < n; ++i)
+    if (in[i] == nullptr || out[i] == nullptr) return fail(FDD_E_INVALID, "null input or output of beam " + std::to_string(i));
+  hipStream_t st = (hipStream_t)stream;
+  const bool same = b->ready && std::equal(in, in + n, b->last_in.begin()) && std::equal(out, out + n, b->last_out.begin());
+  if (!same) {
+    b->ready = false;
+    hipError_t e = hipStreamSynchronize(st);            // earlier calls still read the descriptors
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    bool tune = false;
+    for (const Class& c : b->classes) tune = tune || !c.settled;
+    fdd_status s = tune ? autotune(b, in, out, st) : FDD_OK;
+    if (s == FDD_OK) s = fill(b, in, out);
+    if (s == FDD_OK) s = upload(b);
+    if (s != FDD_OK) return s;
+    if (!(b->flags & FDD_BATCH_NO_GRAPH)) {
+      if (b->exec != nullptr) (void)hipGraphExecDestroy(b->exec);
+      if (b->graph != nullptr) (void)hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+      e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+      s = enqueue_all(b, in, b->cap);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(b->cap, &g);
+      if (s != FDD_OK) {
+        if (g != nullptr) (void)hipGraphDestroy(g);
+        return s;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      b->graph = g;
+      e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->last_in.assign(in, in + n);
+    b->last_out.assign(out, out + n);
+    b->ready = true;
+  }
+  if (b->flags & FDD_BATCH_NO_GRAPH) return enqueue_all(b, in, st);
+  hipError_t e = hipGraphLaunch(b->exec, st);
+  return e == hipSuccess ? FDD_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+fdd_status fdd_batch_info(fdd_batch_t b, int32_t* n_waves, size_t* scratch_bytes, size_t* table_bytes) {
+  if (b == nullptr) return fail(FDD_E_INVALID, "null batch");
+  if (n_waves != nullptr) *n_waves = b->n_waves;
+  if (scratch_bytes != nullptr) *scratch_bytes = b->scr_bytes;
+  if (table_bytes != nullptr) *table_bytes = b->tab_bytes;
+  return FDD_OK;
+}
+
+fdd_status fdd_batch_describe(fdd_batch_t b, char* buf, size_t len, size_t* needed) {
+  if (b == nullptr) return fail(FDD_E_INVALID, "null batch");
+  std::ostringstream o;
+  o << "{\"arch\": \"" << b->arch << "\", \"waves\": " << b->n_waves << ", \"scratch_bytes\": " << b->scr_bytes
+    << ", \"table_bytes\": " << b->tab_bytes << ", \"graph\": " << ((b->flags & FDD_BATCH_NO_GRAPH) ? "false" : "true")
+    << ",\n \"beams\": [";
+  for (size_t i = 0; i < b->beams.size(); ++i)
+    o << (i ? ", " : "") << "{\"wave\": " << b->beams[i].wave << ", \"class\": " << b->beams[i].cls
+      << ", \"scratch_bytes\": " << b->beams[i].bytes << "}";
+  o << "],\n \"classes\": [";
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    const Class& k = b->classes[c];
+    o << (c ? ",\n  " : "\n  ") << "{\"key\": \"" << k.key << "\", \"choice\": \"" << k.cands[(size_t)k.choice].name()
+      << "\", \"settled\": " << (k.settled ? "true" : "false") << ", \"candidates\": {";
+    for (size_t j = 0; j < k.cands.size(); ++j)
+      o << (j ? ", " : "") << "\"" << k.cands[j].name() << "\": " << (k.ms[j] >= 0.0f ? std::to_string(k.ms[j]) : "null");
+    o << "}}";
+  }
+  o << "],\n \"launches\": [";
+  static const char* names[] = {"transpose", "r2c", "phasor", "c2r"};
+  for (size_t i = 0; i < b->launches.size(); ++i) {
+    const Launch& l = b->launches[i];
+    o << (i ? ", " : "") << "{\"stage\": \"" << names[l.stage] << "\", \"wave\": " << l.wave
+      << ", \"beams\": " << l.beams.size() << ", \"tiles\": " << l.total;
+    if (l.stage == kPhasor) o << ", \"class\": " << l.cls;
+    o << "}";
+  }
+  o << "]}";
+  const std::string s = o.str();
+  if (needed != nullptr) *needed = s.size() + 1;
+  if (buf == nullptr || len < s.size() + 1) return fail(FDD_E_INVALID, "describe buffer too small");
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return FDD_OK;
+}
+
+fdd_status fdd_batch_destroy(fdd_batch_t b) {
+  if (b == nullptr) return FDD_OK;
+  release(b);
+  delete b;
+  return FDD_OK;
+}
+
+}  // extern "C"

@@ -63,7 +63,83 @@ struct PhasorArgs {
   int log_len = 0;                  // log2 L
   float dc_add = 0.0f;              // added to Re Y at bin 0 before power (8-bit zero point)
   int tile_variant = 0;             // matrix-core tile shape (0 = default)
+  int n_dmt = 0, n_bb = 0;          // grouped launches: DM tiles and bin blocks of this beam
 };
+
+// Grouped launch over several beams (the batched form): tiles [prefix[b], prefix[b+1]) belong
+// to beam b, whose arguments are beams[b].  For the phasor sums each range is a multiple of 8
+// long, so that a tile's beam-local id modulo 8 equals its global id modulo 8.
+template <class Args>
+struct Group {
+  const Args* beams = nullptr;        // device array [n_beams]
+  const int* prefix = nullptr;        // device array [n_beams + 1], ascending, prefix[0] = 0
+  unsigned int* counters = nullptr;   // persistent launches: 8 ticket counters, zero at launch
+  int n_beams = 0;
+  int total = 0;                      // prefix[n_beams]
+};
+
+// Beam that owns tile `t`: the last b with prefix[b] <= t (binary search).
+__device__ __forceinline__ int group_beam(const int* prefix, int n_beams, int t) {
+  int lo = 0, hi = n_beams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Load a workgroup-uniform struct from device memory into scalar registers (dword by dword
+// through readfirstlane), so that a beam's arguments cost no vector registers.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized struct expected");
+  constexpr int kWords = (int)(sizeof(T) / 4);
+  union U {
+    T t;
+    int w[kWords];
+    __device__ U() {}
+  } u;
+  const int* src = reinterpret_cast<const int*>(p);
+#pragma unroll
+  for (int i = 0; i < kWords; ++i) u.w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return u.t;
+}
+
+// Tile loops of the grouped phasor sums.  Non-persistent: one workgroup per tile, tile id =
+// linear workgroup id (the hardware balances).  Persistent: workgroup p serves the tiles congruent to p modulo 8, claiming them
+// one at a time from ticket counter p mod 8; the grid is a multiple of 8 workgroups, so every
+// tile below `total` is claimed exactly once, each claim names a tile on the XCD that the
+// hardware gives workgroup p (workgroups are dispatched round-robin over the 8 XCDs), and the
+// tiles of one XCD are balanced dynamically.  Every workgroup leaves once its counter passes
+// `total`.
+template <bool PERSIST, class Body>
+__device__ __forceinline__ void grouped_tiles(unsigned int* counters, int total, Body&& body) {
+  if constexpr (!PERSIST) {
+    const int t = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (t < total) body(t, (int)threadIdx.x);
+    return;
+  }
+  __shared__ int ticket;
+  const int xcd = (int)(blockIdx.x & 7u);
+  for (;;) {
+    __syncthreads();                          // the previous tile is done with LDS and `ticket`
+    if (threadIdx.x == 0) ticket = (int)atomicAdd(counters + xcd, 1u) * 8 + xcd;
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(ticket);   // uniform: keeps beam arguments scalar
+    if (t >= total) break;
+    // the thread index reaches the body as an opaque value, so that nothing derived from it is
+    // hoisted out of the loop and held in registers across tiles
+    int tid = (int)threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    body(t, tid);
+  }
+}
+
+// Workgroups of a persistent launch: what fits on the device at once (at most `cap`), as a
+// multiple of 8 and at least 8.
+int persistent_blocks(const void* kernel, int threads, int64_t cap);
+
 
 // A 1-D sequence of `blocks` workgroups laid out as a 2-D grid whose linear order
 // (y * gridDim.x + x) is the sequence: the work-item count of one grid dimension must stay
@@ -74,6 +150,13 @@ inline dim3 linear_grid(int64_t blocks) {
   return dim3((unsigned)row, (unsigned)((blocks + row - 1) / row));
 }
 
+// Grid of a grouped phasor launch: every tile (non-persistent) or what fits (persistent).
+inline dim3 grouped_grid(bool persist, const void* kernel, int total) {
+  return persist ? dim3((unsigned)persistent_blocks(kernel, 256, ((int64_t)total + 7) / 8 * 8))
+                 : linear_grid(total);
+}
+
+hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t st);
 hipError_t launch_transpose_u8(const uint8_t* in, uint8_t* out, int64_t n_samp, int n_chan, hipStream_t st);
 hipError_t launch_r2c(int log_n, const FftArgs& a, hipStream_t st);
 hipError_t launch_c2r(int log_n, const FftArgs& a, hipStream_t st);
@@ -85,6 +168,21 @@ hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st);
 hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st);
 bool phasor_mfma_f32_supported(int n_chunks);
 bool phasor_split_supported(int n_chunks);
+
+// Grouped launches of the batched form.  Tiles per beam (for the prefix sums) come from the
+// *_tiles functions, which also fill a.n_dmt / a.n_bb where the kernel needs them.
+hipError_t launch_r2c_grouped(int log_n, bool u8, const Group<FftArgs>& g, hipStream_t st);
+hipError_t launch_c2r_grouped(int log_n, const Group<FftArgs>& g, hipStream_t st);
+int64_t fft_grouped_tiles(const FftArgs& a);
+int64_t phasor_mfma_f32_tiles(PhasorArgs* a, int variant);
+hipError_t launch_phasor_mfma_f32_grouped(int nt, int variant, bool persist, const Group<PhasorArgs>& g,
+                                          hipStream_t st);
+int64_t phasor_split_tiles(PhasorArgs* a);
+hipError_t launch_phasor_split_grouped(bool bf16, int nt, bool persist, const Group<PhasorArgs>& g,
+                                       hipStream_t st);
+int64_t phasor_valu_tiles(PhasorArgs* a, int nk);
+hipError_t launch_phasor_valu_grouped(int nk, const Group<PhasorArgs>& g, hipStream_t st);
+constexpr int kMfmaF32Variants = 5;
 
 // Byte offsets of the workspace regions (256-byte aligned).
 struct WorkspaceLayout {
@@ -121,6 +219,10 @@ struct fdd_plan_s {
 };
 
 namespace fdd {
+// Planner tables (float64 on the host): twiddles exp(-2 pi i j / L), j < L, and the phase
+// increments and step phasors of every (channel, DM), channel-major.
+void twiddle_table(int64_t L, std::vector<float2>* out);
+void phase_table(const fdd_plan_s* p, std::vector<uint4>* out);
 void set_error(const std::string& msg);
 fdd_status fail(fdd_status s, const std::string& msg);
 fdd_status hip_fail(hipError_t e, const char* what);

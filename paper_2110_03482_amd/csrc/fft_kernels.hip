@@ -70,20 +70,19 @@ __global__ void k_zero_u32(unsigned int* p, int n) {
 }
 
 template <int LOGN, int LOGE, bool U8>
-__global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_r2c(
-    const uint8_t* __restrict__ in_u8,   // [n_chan][n_samp] (transposed) or null
-    const float* __restrict__ in_f32,    // [n_chan][n_samp] or null
-    float2* __restrict__ X,              // [n_chan][n_chunks][pitch]
-    const float2* __restrict__ twL,      // exp(-2 pi i j / L), j < L
-    int64_t n_samp, int64_t stride, int64_t pitch, int n_chunks,
-    unsigned int* __restrict__ l1max) {  // per chunk: max over channels of sum |x| (float bits), or null
+__device__ __forceinline__ void r2c_body(const FftArgs& a, const int k, const int c) {
   using F = BlockFft<LOGN, LOGE, false>;
   constexpr int N = F::N, E = F::E, T = F::T;
   constexpr int64_t L = 2 * (int64_t)N;
   __shared__ float lds[LdsSize<LOGN>::floats];
+  const uint8_t* __restrict__ in_u8 = a.in_u8;
+  const float* __restrict__ in_f32 = a.in_f32;
+  float2* __restrict__ X = a.X;
+  const float2* __restrict__ twL = a.twL;
+  const int64_t n_samp = a.n_samp, stride = a.stride, pitch = a.pitch;
+  const int n_chunks = a.n_chunks;
+  unsigned int* __restrict__ l1max = a.l1max;
   const int t = threadIdx.x;
-  const int k = blockIdx.x;
-  const int c = blockIdx.y;
   const int64_t s0 = (int64_t)k * stride;
   const float zp = (U8 && s0 + L <= n_samp) ? 128.0f : 0.0f;
   float2 v[E];
@@ -127,21 +126,40 @@ __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_r2c(
   if (t == 0) dst[N] = make_float2(v[0].x - v[0].y, 0.0f);   // Nyquist bin
 }
 
+template <int LOGN, int LOGE, bool U8>
+__global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_r2c(FftArgs a) {
+  r2c_body<LOGN, LOGE, U8>(a, blockIdx.x, blockIdx.y);
+}
+
+// Batched form: one workgroup per (beam, channel, chunk) series; all beams of the launch
+// share L.
+template <int LOGN, int LOGE, bool U8>
+__global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_r2c_grouped(Group<FftArgs> g) {
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (bid >= g.total) return;
+  const int b = group_beam(g.prefix, g.n_beams, bid);
+  const FftArgs a = g.beams[b];
+  const int lid = bid - g.prefix[b];
+  if (lid >= a.n_chunks * a.n_rows) return;
+  r2c_body<LOGN, LOGE, U8>(a, lid % a.n_chunks, lid / a.n_chunks);
+}
+
 // ----------------------------------------------------------------------------- inverse
 
 template <int LOGN, int LOGE>
-__global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_c2r(
-    const float* __restrict__ Yr, const float* __restrict__ Yi,   // [n_dm][n_chunks][pitch] planes
-    float* __restrict__ out,                                      // [n_dm][n_samp]
-    const float2* __restrict__ twL, int64_t n_samp, int64_t stride, int64_t keep, int64_t pitch,
-    int n_chunks, float add_full) {
+__device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const int dm) {
   using F = BlockFft<LOGN, LOGE, true>;
   constexpr int N = F::N, E = F::E, T = F::T;
   constexpr int64_t L = 2 * (int64_t)N;
   __shared__ float lds[LdsSize<LOGN>::floats];
+  const float* __restrict__ Yr = a.Yr;
+  const float* __restrict__ Yi = a.Yi;
+  float* __restrict__ out = a.out;
+  const int64_t n_samp = a.n_samp, stride = a.stride, keep = a.keep, pitch = a.pitch;
+  const int n_chunks = a.n_chunks;
+  const float add_full = a.add_full;
+  const float2* __restrict__ twL = a.twL;
   const int t = threadIdx.x;
-  const int k = blockIdx.x;
-  const int dm = blockIdx.y;
   const int64_t row = ((int64_t)dm * n_chunks + k) * pitch;
   const float* yr = Yr + row;
   const float* yi = Yi + row;
@@ -171,6 +189,22 @@ __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_c2r(
     if (s < lim) dst[s] = v[q].x + add;
     if (s + 1 < lim) dst[s + 1] = v[q].y + add;
   }
+}
+
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_c2r(FftArgs a) {
+  c2r_body<LOGN, LOGE>(a, blockIdx.x, blockIdx.y);
+}
+
+template <int LOGN, int LOGE>
+__global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_c2r_grouped(Group<FftArgs> g) {
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (bid >= g.total) return;
+  const int b = group_beam(g.prefix, g.n_beams, bid);
+  const FftArgs a = g.beams[b];
+  const int lid = bid - g.prefix[b];
+  if (lid >= a.n_chunks * a.n_rows) return;
+  c2r_body<LOGN, LOGE>(a, lid % a.n_chunks, lid / a.n_chunks);
 }
 
 // ----------------------------------------------------------------------------- long transforms
@@ -461,11 +495,27 @@ hipError_t launch_r2c_n(const FftArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3((a.n_chunks + 255) / 256), dim3(256), 0, st, a.l1max, a.n_chunks);
   }
   if (a.in_u8 != nullptr)
-    hipLaunchKernelGGL((k_r2c<LOGN, LOGE, true>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a.in_u8, a.in_f32, a.X,
-                       a.twL, a.n_samp, a.stride, a.pitch, a.n_chunks, a.l1max);
+    hipLaunchKernelGGL((k_r2c<LOGN, LOGE, true>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a);
   else
-    hipLaunchKernelGGL((k_r2c<LOGN, LOGE, false>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a.in_u8, a.in_f32, a.X,
-                       a.twL, a.n_samp, a.stride, a.pitch, a.n_chunks, a.l1max);
+    hipLaunchKernelGGL((k_r2c<LOGN, LOGE, false>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int LOGN>
+hipError_t launch_r2c_grouped_n(bool u8, const Group<FftArgs>& g, hipStream_t st) {
+  constexpr int LOGE = fft_loge<LOGN>();
+  const dim3 grid = linear_grid(g.total);
+  if (u8)
+    hipLaunchKernelGGL((k_r2c_grouped<LOGN, LOGE, true>), grid, dim3(1 << (LOGN - LOGE)), 0, st, g);
+  else
+    hipLaunchKernelGGL((k_r2c_grouped<LOGN, LOGE, false>), grid, dim3(1 << (LOGN - LOGE)), 0, st, g);
+  return hipGetLastError();
+}
+
+template <int LOGN>
+hipError_t launch_c2r_grouped_n(const Group<FftArgs>& g, hipStream_t st) {
+  constexpr int LOGE = fft_loge<LOGN>();
+  hipLaunchKernelGGL((k_c2r_grouped<LOGN, LOGE>), linear_grid(g.total), dim3(1 << (LOGN - LOGE)), 0, st, g);
   return hipGetLastError();
 }
 
@@ -473,11 +523,17 @@ template <int LOGN>
 hipError_t launch_c2r_n(const FftArgs& a, hipStream_t st) {
   constexpr int LOGE = fft_loge<LOGN>();
   dim3 grid((unsigned)a.n_chunks, (unsigned)a.n_rows);
-  hipLaunchKernelGGL((k_c2r<LOGN, LOGE>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a.Yr, a.Yi, a.out, a.twL,
-                     a.n_samp, a.stride, a.keep, a.pitch, a.n_chunks, a.add_full);
+  hipLaunchKernelGGL((k_c2r<LOGN, LOGE>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a);
   return hipGetLastError();
 }
 }  // namespace
+
+hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, (int)n);
+  return hipGetLastError();
+}
 
 hipError_t launch_transpose_u8(const uint8_t* in, uint8_t* out, int64_t n_samp, int n_chan, hipStream_t st) {
   dim3 grid((unsigned)((n_samp + 63) / 64), (unsigned)((n_chan + 63) / 64));
@@ -515,6 +571,44 @@ hipError_t launch_c2r(int log_n, const FftArgs& a, hipStream_t st) {
     case 13: return launch_c2r_n<13>(a, st);
     case 14: return launch_c2r_n<14>(a, st);
     case 15: return launch_c2r_n<15>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int64_t fft_grouped_tiles(const FftArgs& a) { return (int64_t)a.n_chunks * a.n_rows; }
+
+hipError_t launch_r2c_grouped(int log_n, bool u8, const Group<FftArgs>& g, hipStream_t st) {
+  if (g.total <= 0) return hipSuccess;
+  switch (log_n) {
+    case 5: return launch_r2c_grouped_n<5>(u8, g, st);
+    case 6: return launch_r2c_grouped_n<6>(u8, g, st);
+    case 7: return launch_r2c_grouped_n<7>(u8, g, st);
+    case 8: return launch_r2c_grouped_n<8>(u8, g, st);
+    case 9: return launch_r2c_grouped_n<9>(u8, g, st);
+    case 10: return launch_r2c_grouped_n<10>(u8, g, st);
+    case 11: return launch_r2c_grouped_n<11>(u8, g, st);
+    case 12: return launch_r2c_grouped_n<12>(u8, g, st);
+    case 13: return launch_r2c_grouped_n<13>(u8, g, st);
+    case 14: return launch_r2c_grouped_n<14>(u8, g, st);
+    case 15: return launch_r2c_grouped_n<15>(u8, g, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_c2r_grouped(int log_n, const Group<FftArgs>& g, hipStream_t st) {
+  if (g.total <= 0) return hipSuccess;
+  switch (log_n) {
+    case 5: return launch_c2r_grouped_n<5>(g, st);
+    case 6: return launch_c2r_grouped_n<6>(g, st);
+    case 7: return launch_c2r_grouped_n<7>(g, st);
+    case 8: return launch_c2r_grouped_n<8>(g, st);
+    case 9: return launch_c2r_grouped_n<9>(g, st);
+    case 10: return launch_c2r_grouped_n<10>(g, st);
+    case 11: return launch_c2r_grouped_n<11>(g, st);
+    case 12: return launch_c2r_grouped_n<12>(g, st);
+    case 13: return launch_c2r_grouped_n<13>(g, st);
+    case 14: return launch_c2r_grouped_n<14>(g, st);
+    case 15: return launch_c2r_grouped_n<15>(g, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -23,6 +23,9 @@
 // Workgroups are numbered so that the DM tiles of one bin block run back to back on the same
 // XCD (hardware dispatches workgroup i to XCD i mod 8), so the bin block's data is served
 // from that XCD's L2 after the first read.
+#include <map>
+#include <mutex>
+
 #include "device_math.h"
 #include "fdd_internal.h"
 
@@ -37,7 +40,9 @@ constexpr int kXcds = 8;
 // FB bins per workgroup, KC channels per LDS stage, NT 16-column tiles (2N <= 16 NT),
 // MW 16-DM sub-tiles per wave (64 MW DMs per workgroup).
 template <int NT, int FB, int KC, int MW>
-__global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt, int n_bb) {
+__device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const int bid, const int n_dmt,
+                                                     const int n_bb,
+    const int tid) {
   constexpr int kDmTile = 64 * MW;
   constexpr int NCOL = NT * 16;
   // per-channel stride padded by 16 floats so that the four channels read by one MFMA step
@@ -49,15 +54,12 @@ __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt
   __shared__ float bre[PLANE];
   __shared__ float bim[PLANE];
 
-  // linear workgroup id; the grid is 2-D only to keep each dimension below 2^32 work-items
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
   const int bb = (slot / n_dmt) * kXcds + xcd;
   const int dmt = slot % n_dmt;
   if (bb >= n_bb) return;                     // uniform per workgroup, before any barrier
   const int fb0 = bb * FB;
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int N = a.n_chunks;
@@ -186,6 +188,50 @@ __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt
   }
 }
 
+// linear workgroup id; grids are 2-D only to keep each dimension below 2^32 work-items
+__device__ __forceinline__ int linear_block() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+template <int NT, int FB, int KC, int MW>
+__global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt, int n_bb) {
+  phasor_mfma_f32_body<NT, FB, KC, MW>(a, linear_block(), n_dmt, n_bb, threadIdx.x);
+}
+
+// Batched form: the tiles of every beam of the group, one per workgroup or persistent.
+template <int NT, int FB, int KC, int MW, bool PERSIST>
+__global__ __launch_bounds__(256) void k_phasor_mfma_f32_grouped(Group<PhasorArgs> g) {
+  grouped_tiles<PERSIST>(g.counters, g.total, [&](int t, int tid) {
+    const int b = group_beam(g.prefix, g.n_beams, t);
+    const PhasorArgs a = PERSIST ? load_uniform(g.beams + b) : g.beams[b];
+    phasor_mfma_f32_body<NT, FB, KC, MW>(a, t - g.prefix[b], a.n_dmt, a.n_bb, tid);
+  });
+}
+
+int persistent_blocks(const void* kernel, int threads, int64_t cap) {
+  // resident workgroups per device, per kernel (queried once: launches may be under capture)
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int64_t> resident;
+  int64_t n = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = resident.find({kernel, threads});
+    if (it != resident.end()) {
+      n = it->second;
+    } else {
+      int dev = 0, cus = 0, per_cu = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) == hipSuccess)
+        n = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+      else
+        n = 8;
+      resident.emplace(std::make_pair(kernel, threads), n);
+    }
+  }
+  if (n > cap) n = cap;
+  n = n / 8 * 8;
+  return n < 8 ? 8 : (int)n;
+}
+
 bool phasor_mfma_f32_supported(int n_chunks) { return n_chunks >= 3 && n_chunks <= 24; }
 
 namespace {
@@ -216,6 +262,55 @@ hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st) {
     case 3: return launch_tile<4, 8, 2>(a, st);
     case 4: return launch_tile<4, 16, 2>(a, st);
     default: return launch_tile<8, 8, 1>(a, st);
+  }
+}
+
+namespace {
+struct TileShape {
+  int fb, mw;
+};
+constexpr TileShape kShapes[kMfmaF32Variants] = {{8, 1}, {16, 1}, {8, 1}, {4, 2}, {4, 2}};
+
+template <int NT, int FB, int KC, int MW, bool P>
+hipError_t launch_grouped_nt(const Group<PhasorArgs>& g, hipStream_t st) {
+  const void* k = (const void*)k_phasor_mfma_f32_grouped<NT, FB, KC, MW, P>;
+  hipLaunchKernelGGL((k_phasor_mfma_f32_grouped<NT, FB, KC, MW, P>), grouped_grid(P, k, g.total), dim3(256), 0, st,
+                     g);
+  return hipGetLastError();
+}
+
+template <int FB, int KC, int MW>
+hipError_t launch_grouped_tile(int nt, bool persist, const Group<PhasorArgs>& g, hipStream_t st) {
+  switch (nt * 2 + (persist ? 1 : 0)) {
+    case 2: return launch_grouped_nt<1, FB, KC, MW, false>(g, st);
+    case 3: return launch_grouped_nt<1, FB, KC, MW, true>(g, st);
+    case 4: return launch_grouped_nt<2, FB, KC, MW, false>(g, st);
+    case 5: return launch_grouped_nt<2, FB, KC, MW, true>(g, st);
+    case 6: return launch_grouped_nt<3, FB, KC, MW, false>(g, st);
+    case 7: return launch_grouped_nt<3, FB, KC, MW, true>(g, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+int64_t phasor_mfma_f32_tiles(PhasorArgs* a, int variant) {
+  if (variant < 0 || variant >= kMfmaF32Variants) variant = 0;
+  const TileShape sh = kShapes[variant];
+  a->n_dmt = (a->n_dm + 64 * sh.mw - 1) / (64 * sh.mw);
+  a->n_bb = (a->n_bins + sh.fb - 1) / sh.fb;
+  return (int64_t)a->n_dmt * ((a->n_bb + kXcds - 1) / kXcds * kXcds);
+}
+
+// Same tile variants as launch_phasor_mfma_f32; nt = ceil(2 N / 16) of every beam in the group.
+hipError_t launch_phasor_mfma_f32_grouped(int nt, int variant, bool persist, const Group<PhasorArgs>& g,
+                                          hipStream_t st) {
+  if (g.total <= 0) return hipSuccess;
+  switch (variant) {
+    case 1: return launch_grouped_tile<16, 8, 1>(nt, persist, g, st);
+    case 2: return launch_grouped_tile<8, 16, 1>(nt, persist, g, st);
+    case 3: return launch_grouped_tile<4, 8, 2>(nt, persist, g, st);
+    case 4: return launch_grouped_tile<4, 16, 2>(nt, persist, g, st);
+    default: return launch_grouped_tile<8, 8, 1>(nt, persist, g, st);
   }
 }
 

@@ -83,7 +83,9 @@ __device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) |
 }  // namespace
 
 template <bool BF, int NT, int FB>
-__global__ __launch_bounds__(256, 2) void k_phasor_split(PhasorArgs a, int n_dmt, int n_bb) {
+__device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int bid, const int n_dmt,
+                                                  const int n_bb,
+    const int tid) {
   using H = HalfOps<BF>;
   typedef typename H::V8 V8;
   constexpr int KC = 16;                 // channels per LDS stage = one MFMA contraction step
@@ -98,15 +100,12 @@ __global__ __launch_bounds__(256, 2) void k_phasor_split(PhasorArgs a, int n_dmt
   __shared__ uint4 llo[PLANEW / 4];
   __shared__ float colscale[32];
 
-  // linear workgroup id; the grid is 2-D only to keep each dimension below 2^32 work-items
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
   const int bb = (slot / n_dmt) * kXcds + xcd;
   const int dmt = slot % n_dmt;
   if (bb >= n_bb) return;                // uniform per workgroup, before any barrier
   const int fb0 = bb * FB;
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int N = a.n_chunks;
@@ -253,6 +252,24 @@ __global__ __launch_bounds__(256, 2) void k_phasor_split(PhasorArgs a, int n_dmt
   }
 }
 
+// linear workgroup id; grids are 2-D only to keep each dimension below 2^32 work-items
+__device__ __forceinline__ int linear_block_s() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+template <bool BF, int NT, int FB>
+__global__ __launch_bounds__(256, 2) void k_phasor_split(PhasorArgs a, int n_dmt, int n_bb) {
+  phasor_split_body<BF, NT, FB>(a, linear_block_s(), n_dmt, n_bb, threadIdx.x);
+}
+
+// Batched form: the tiles of every beam of the group, one per workgroup or persistent.
+template <bool BF, int NT, int FB, bool PERSIST>
+__global__ __launch_bounds__(256, 2) void k_phasor_split_grouped(Group<PhasorArgs> g) {
+  grouped_tiles<PERSIST>(g.counters, g.total, [&](int t, int tid) {
+    const int b = group_beam(g.prefix, g.n_beams, t);
+    const PhasorArgs a = PERSIST ? load_uniform(g.beams + b) : g.beams[b];
+    phasor_split_body<BF, NT, FB>(a, t - g.prefix[b], a.n_dmt, a.n_bb, tid);
+  });
+}
+
 bool phasor_split_supported(int n_chunks) { return n_chunks >= 1 && n_chunks <= 24; }
 
 namespace {
@@ -278,6 +295,42 @@ hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st) {
   if (!phasor_split_supported(a.n_chunks)) return hipErrorInvalidValue;
   if (a.P != nullptr && a.n_chunks != 1) return hipErrorInvalidValue;
   return bf16 ? launch_split_fb<true, 8>(a, st) : launch_split_fb<false, 8>(a, st);
+}
+
+namespace {
+constexpr int kSplitFb = 8;
+
+template <bool BF, int NT, bool P>
+hipError_t launch_split_grouped_nt(const Group<PhasorArgs>& g, hipStream_t st) {
+  const void* k = (const void*)k_phasor_split_grouped<BF, NT, kSplitFb, P>;
+  hipLaunchKernelGGL((k_phasor_split_grouped<BF, NT, kSplitFb, P>), grouped_grid(P, k, g.total), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+template <bool BF>
+hipError_t launch_split_grouped_bf(int nt, bool persist, const Group<PhasorArgs>& g, hipStream_t st) {
+  switch (nt * 2 + (persist ? 1 : 0)) {
+    case 2: return launch_split_grouped_nt<BF, 1, false>(g, st);
+    case 3: return launch_split_grouped_nt<BF, 1, true>(g, st);
+    case 4: return launch_split_grouped_nt<BF, 2, false>(g, st);
+    case 5: return launch_split_grouped_nt<BF, 2, true>(g, st);
+    case 6: return launch_split_grouped_nt<BF, 3, false>(g, st);
+    case 7: return launch_split_grouped_nt<BF, 3, true>(g, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
+int64_t phasor_split_tiles(PhasorArgs* a) {
+  a->n_dmt = (a->n_dm + 63) / 64;
+  a->n_bb = (a->n_bins + kSplitFb - 1) / kSplitFb;
+  return (int64_t)a->n_dmt * ((a->n_bb + kXcds - 1) / kXcds * kXcds);
+}
+
+hipError_t launch_phasor_split_grouped(bool bf16, int nt, bool persist, const Group<PhasorArgs>& g,
+                                       hipStream_t st) {
+  if (g.total <= 0) return hipSuccess;
+  return bf16 ? launch_split_grouped_bf<true>(nt, persist, g, st) : launch_split_grouped_bf<false>(nt, persist, g, st);
 }
 
 }  // namespace fdd

@@ -23,12 +23,12 @@ constexpr int kDmThreads = 4;     // threads along DMs per block
 }
 
 template <int FV, int NK>
-__global__ __launch_bounds__(256) void k_phasor_valu(PhasorArgs a) {
+__device__ __forceinline__ void phasor_valu_body(const PhasorArgs& a, const int bx, const int by, const int bz) {
   const int tx = threadIdx.x % kBinThreads;
   const int ty = threadIdx.x / kBinThreads;
-  const int f0 = (blockIdx.x * kBinThreads + tx) * FV;
-  const int dm = blockIdx.y * kDmThreads + ty;
-  const int k0 = blockIdx.z * NK;
+  const int f0 = (bx * kBinThreads + tx) * FV;
+  const int dm = by * kDmThreads + ty;
+  const int k0 = bz * NK;
   if (dm >= a.n_dm || f0 >= a.n_bins) return;   // no barriers in this kernel
   float2 acc[NK][FV];
 #pragma unroll
@@ -82,8 +82,44 @@ __global__ __launch_bounds__(256) void k_phasor_valu(PhasorArgs a) {
   }
 }
 
+template <int FV, int NK>
+__global__ __launch_bounds__(256) void k_phasor_valu(PhasorArgs a) {
+  phasor_valu_body<FV, NK>(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Batched form: tile t of beam b is block (t mod n_bb, (t / n_bb) mod n_dmt, t / (n_bb n_dmt))
+// of that beam's own launch.
+template <int FV, int NK>
+__global__ __launch_bounds__(256) void k_phasor_valu_grouped(Group<PhasorArgs> g) {
+  const int t = blockIdx.y * gridDim.x + blockIdx.x;
+  if (t >= g.total) return;
+  const int b = group_beam(g.prefix, g.n_beams, t);
+  const PhasorArgs& a = g.beams[b];
+  const int lt = t - g.prefix[b];
+  phasor_valu_body<FV, NK>(a, lt % a.n_bb, (lt / a.n_bb) % a.n_dmt, lt / (a.n_bb * a.n_dmt));
+}
+
+namespace {
+constexpr int kFv = 16;
+}
+
+int64_t phasor_valu_tiles(PhasorArgs* a, int nk) {
+  a->n_bb = (a->n_bins + kBinThreads * kFv - 1) / (kBinThreads * kFv);
+  a->n_dmt = (a->n_dm + kDmThreads - 1) / kDmThreads;
+  return (int64_t)a->n_bb * a->n_dmt * ((a->n_chunks + nk - 1) / nk);
+}
+
+hipError_t launch_phasor_valu_grouped(int nk, const Group<PhasorArgs>& g, hipStream_t st) {
+  if (g.total <= 0) return hipSuccess;
+  const dim3 grid = linear_grid(g.total), block(kBinThreads * kDmThreads);
+  if (nk == 1) hipLaunchKernelGGL((k_phasor_valu_grouped<kFv, 1>), grid, block, 0, st, g);
+  else if (nk == 4) hipLaunchKernelGGL((k_phasor_valu_grouped<kFv, 4>), grid, block, 0, st, g);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_phasor_valu(const PhasorArgs& a, hipStream_t st) {
-  constexpr int FV = 16;
+  constexpr int FV = kFv;
   dim3 block(kBinThreads * kDmThreads);
   const unsigned gx = (unsigned)((a.n_bins + kBinThreads * FV - 1) / (kBinThreads * FV));
   const unsigned gy = (unsigned)((a.n_dm + kDmThreads - 1) / kDmThreads);

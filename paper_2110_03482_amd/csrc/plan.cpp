@@ -54,7 +54,7 @@ static double kappa_of(double f_mhz, double ref_mhz, double tsamp_s) {
 // (d mod L) << (64 - log2 L) for nearest-sample delays), and the unit phasor of one bin step,
 // exp(+2 pi i inc / 2^64), evaluated in float64.  Channel-major, so that the DM lanes of a
 // kernel read consecutive entries.
-static void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) {
+void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) {
   const size_t nc = p->kappa.size(), nd = p->dms.size();
   out->resize(nc * nd);
   const int lg = p->log_len;
@@ -87,14 +87,19 @@ static void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) {
   }
 }
 
+void twiddle_table(int64_t L, std::vector<float2>* out) {
+  out->resize((size_t)L);
+  for (int64_t j = 0; j < L; ++j) {
+    // exp(-2 pi i j / L), evaluated in float64
+    const double a = -2.0 * M_PI * (double)j / (double)L;
+    (*out)[(size_t)j] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+}
+
 static fdd_status upload_tables(fdd_plan_s* p) {
   const WorkspaceLayout& w = p->ws;
-  std::vector<float2> tw((size_t)p->L);
-  for (int64_t j = 0; j < p->L; ++j) {
-    // exp(-2 pi i j / L) in float64, reduced to the first octant by symmetry for accuracy
-    const double a = -2.0 * M_PI * (double)j / (double)p->L;
-    tw[(size_t)j] = make_float2((float)std::cos(a), (float)std::sin(a));
-  }
+  std::vector<float2> tw;
+  twiddle_table(p->L, &tw);
   hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), w.tw_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddles)");
   std::vector<uint4> tab;

@@ -145,3 +145,24 @@ def test_kernel_selection():
     w2 = W.tiny_random(1, 16, 5000, 8, 1024, False, dm_max=3.0)
     p = _dry(w2)
     assert p.geometry.n_chunks >= 3 and p.kernel == "mfma_f32"
+
+
+def test_batch_rejects_without_device_calls():
+    lib = fdd.library()
+    d = fdd.BatchDesc()
+    out = ctypes.c_void_p()
+    assert lib.fdd_batch_create(0, None, ctypes.byref(d), ctypes.byref(out)) == 1
+    assert lib.fdd_batch_create(1, None, None, None) == 1
+    w = W.small_fp32()
+    p = _dry(w)
+    with pytest.raises(fdd.FddError) as e:
+        fdd.fdd_batch_create([p.handle], d)
+    assert e.value.status == 1 and "dry-run" in str(e.value)
+    d.flags = 1 << 9
+    with pytest.raises(fdd.FddError) as e:
+        fdd.fdd_batch_create([p.handle], d)
+    assert e.value.status == 1 and "flags" in str(e.value)
+    assert lib.fdd_batch_execute(None, None, None, None) == 1
+    assert lib.fdd_batch_info(None, None, None, None) == 1
+    assert lib.fdd_batch_destroy(None) == 0
+    p.close()

@@ -1,0 +1,255 @@
+"""GPU tests of the batched form (fdd_batch_*): many uneven beams through grouped launches.
+
+ - With the autotuner off the batch runs the kernels a single plan would run, so every beam's
+   output must equal fdd_execute of its plan bit for bit, and the oracle to the FP32 bar.
+ - Autotuned batches may pick other tile shapes (another summation order): oracle bar.
+ - The captured graph is replayed several times with eager work in between, and re-captured
+   when the tensors change; every replay is checked.
+ - A small scratch limit splits the beams into memory waves that share one arena.
+ - Beams shaped like the multi-beam workload (L = 2^16, 256-1024 channels, 512-4096 DMs)
+   are checked on sampled rows, and each injected pulse is found at its DM.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fdd = pytest.importorskip("paper_2110_03482_amd")
+
+TOL = 1e-5
+CENTRED_TOL = 2e-4   # 8-bit rows: see the derivation in the single-plan parity tests
+
+# n_chan, n_samp, n_dm, L, single_chunk, input, dm_max, mode  -> chunks (phasor class)
+BEAMS = [
+    (24, 4000, 40, 4096, True, "f32", 5.0, "exact"),     # 1 chunk: VALU, one chunk per thread
+    (16, 3000, 20, 2048, False, "f32", 3.0, "round"),    # 2 chunks: VALU (MFMA candidates when tuned)
+    (20, 9000, 50, 2048, False, "u8", 4.0, "exact"),     # 5 chunks: MFMA, 1 column tile
+    (33, 50000, 65, 4096, False, "f32", 10.0, "exact"),  # 13 chunks: 2 column tiles
+    (40, 30000, 70, 2048, False, "f32", 6.0, "round"),   # 16 chunks: 2 column tiles
+    (28, 40000, 45, 2048, False, "f32", 5.0, "exact"),   # 21 chunks: 3 column tiles
+    (12, 60000, 30, 2048, False, "u8", 2.0, "round"),    # 30 chunks: VALU
+    (8, 70000, 17, 1024, False, "f32", 1.0, "exact"),    # 70 chunks at L = 1024: VALU
+]
+
+
+def rel_err(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.linalg.norm(y - ref, axis=-1) / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+
+
+def rel_err_centred(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.linalg.norm(ref - ref.mean(axis=-1, keepdims=True), axis=-1)
+    return np.linalg.norm(y - ref, axis=-1) / np.maximum(den, 1e-300)
+
+
+def make_beams(specs, precision="fp32", seed0=100):
+    beams = []
+    for i, (n_chan, n_samp, n_dm, L, single, kind, dm_max, mode) in enumerate(specs):
+        w = W.tiny_random(seed0 + i, n_chan, n_samp, n_dm, L, single_chunk=single, input_kind=kind, dm_max=dm_max)
+        x = W.gaussian_u8(n_samp, n_chan, seed0 + i) if kind == "u8" else W.gaussian_f32(n_chan, n_samp, seed0 + i)
+        prec = precision if isinstance(precision, str) else precision[i % len(precision)]
+        beams.append((w, x, mode, prec))
+    return beams
+
+
+def plan_of(w, mode, precision, workspace):
+    return fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, overlap=w.overlap,
+                    single_chunk=w.single_chunk, input=w.input_kind, mode=mode, precision=precision,
+                    workspace=workspace)
+
+
+def single_results(beams, xs):
+    outs = []
+    for (w, _, mode, prec), xd in zip(beams, xs):
+        with plan_of(w, mode, prec, True) as p:
+            outs.append(p.execute(xd).cpu().numpy())
+    torch.cuda.synchronize()
+    return outs
+
+
+def check_oracle(beams, ys, bound):
+    for (w, x, mode, prec), y in zip(beams, ys):
+        ref = O.fdd(x, w.input_kind, w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, overlap=w.overlap,
+                    single_chunk=w.single_chunk, mode=mode)
+        err = rel_err(y, ref)
+        msg = f"{w.name} {w.input_kind} {mode} {prec}: max rel err {err.max():.3e}"
+        if w.input_kind == "u8":
+            ec = rel_err_centred(y, ref)
+            msg += f", centred {ec.max():.3e}"
+            assert ec.max() <= CENTRED_TOL, msg
+        print(msg, flush=True)
+        assert err.max() <= bound, msg
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_single_plans_and_oracle(graph):
+    beams = make_beams(BEAMS)
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+    print(f"batch of {len(beams)} beams, graph={graph}, no autotune", flush=True)
+    plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+    with fdd.Batch(plans, graph=graph, autotune=False) as b:
+        ys = [y.cpu().numpy() for y in b.execute(xs)]
+        desc = b.describe()
+    print(json.dumps(desc["classes"]))
+    keys = {c["key"] for c in desc["classes"]}
+    assert len(keys) == len(desc["classes"]) >= 6
+    singles = single_results(beams, xs)
+    for (w, _, _, _), y, s in zip(beams, ys, singles):
+        assert np.array_equal(y, s), f"{w.name}: batched output differs from fdd_execute"
+    check_oracle(beams, ys, TOL)
+
+
+@pytest.mark.parametrize("precision", [["fp16_split", "bf16_split"]])
+def test_batch_split_precision(precision):
+    specs = [s for s in BEAMS if s[0] not in (12, 8)]          # split kernels take up to 24 chunks
+    beams = make_beams(specs, precision)
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+    print(f"split batch of {len(beams)} beams", flush=True)
+    plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+    with fdd.Batch(plans, autotune=False) as b:
+        ys = [y.cpu().numpy() for y in b.execute(xs)]
+    singles = single_results(beams, xs)
+    for (w, _, _, prec), y, s in zip(beams, ys, singles):
+        assert np.array_equal(y, s), f"{w.name} {prec}: batched output differs from fdd_execute"
+    check_oracle(beams, ys, 1e-4)
+
+
+def test_batch_autotuned_with_cache(tmp_path):
+    beams = make_beams(BEAMS[1:6])
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+    cache = str(tmp_path / "tune.json")
+    plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+    print("autotuned batch", flush=True)
+    with fdd.Batch(plans, tune_cache=cache) as b:
+        ys = [y.cpu().numpy() for y in b.execute(xs)]
+        desc = b.describe()
+    for c in desc["classes"]:
+        print(c["key"], "->", c["choice"], c["candidates"])
+        assert c["settled"]
+        if len(c["candidates"]) > 1:
+            assert c["candidates"][c["choice"]] is not None
+            timed = [v for v in c["candidates"].values() if v is not None]
+            assert len(timed) == len(c["candidates"]) and c["candidates"][c["choice"]] == min(timed)
+    check_oracle(beams, ys, TOL)
+    saved = json.load(open(cache))
+    assert any(k.endswith(c["key"]) for k in saved for c in desc["classes"] if len(c["candidates"]) > 1)
+    # a new batch finds every choice in the cache file and times nothing
+    with fdd.Batch(plans, tune_cache=cache) as b2:
+        d2 = b2.describe()
+        assert all(c["settled"] for c in d2["classes"])
+        assert [c["choice"] for c in d2["classes"]] == [c["choice"] for c in desc["classes"]]
+        ys2 = [y.cpu().numpy() for y in b2.execute(xs)]
+        d3 = b2.describe()
+        assert all(v is None for c in d3["classes"] for v in c["candidates"].values())
+    for y, y2 in zip(ys, ys2):
+        assert np.array_equal(y, y2)
+
+
+def test_graph_replays_and_recapture():
+    specs = [s for s in BEAMS if s[5] == "f32"]
+    beams = make_beams(specs, seed0=300)
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+    plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+    ref_plans = [plan_of(w, mode, prec, True) for w, _, mode, prec in beams]
+    print("graph replays", flush=True)
+    with fdd.Batch(plans, autotune=False) as b:
+        outs = [torch.empty((p.n_dm, p.n_samp), dtype=torch.float32, device="cuda") for p in plans]
+        for rep in range(4):
+            # eager work on the same stream between replays: rescale and shift the inputs in place
+            for x in xs:
+                x.mul_(-0.5).add_(0.25)
+            b.execute(xs, outs)
+            eager = [p.execute(x) for p, x in zip(ref_plans, xs)]
+            torch.cuda.synchronize()
+            for y, e in zip(outs, eager):
+                assert torch.equal(y, e), f"replay {rep} differs from the eager result"
+        # new output tensors: descriptors rewritten and the graph captured again
+        outs2 = b.execute(xs)
+        torch.cuda.synchronize()
+        for y, y2 in zip(outs, outs2):
+            assert torch.equal(y, y2)
+    for p in ref_plans:
+        p.close()
+
+
+def test_memory_waves():
+    beams = make_beams(BEAMS, seed0=500)
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+    plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+    with fdd.Batch(plans, autotune=False) as whole:
+        ys = [y.cpu().numpy() for y in whole.execute(xs)]
+        assert whole.n_waves == 1
+        per_beam = [bm["scratch_bytes"] for bm in whole.describe()["beams"]]
+    # a limit of the largest beam's scratch forces several waves
+    limit = max(per_beam)
+    print(f"memory waves: limit {limit} of {sum(per_beam)} bytes", flush=True)
+    with fdd.Batch(plans, autotune=False, scratch_limit=limit) as waved:
+        assert waved.n_waves > 1
+        assert waved.scratch_bytes <= limit
+        ys2 = [y.cpu().numpy() for y in waved.execute(xs)]
+    for y, y2 in zip(ys, ys2):
+        assert np.array_equal(y, y2)
+
+
+def test_multibeam_shapes_sampled_rows():
+    """Beams shaped like the multi-beam workload (L = 2^16), pulses found at their DMs."""
+    beams = W.batched_beams(4, seed=1, max_log_samp=17)
+    xs, plans, rows = [], [], []
+    for w, pulse_dm, t0 in beams:
+        x = W.gaussian_f32(w.n_chan, w.n_samp, w.seed)
+        offs = O.nearest_sample(O.delays([pulse_dm], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
+        W.inject_pulse_f32(x, offs, t0, 5.0, circular=False)
+        xs.append(x)
+        plans.append(plan_of(w, "exact", "fp32", False))
+        trial = int(np.argmin(np.abs(w.dms - pulse_dm)))
+        rows.append(sorted({0, trial, w.n_dm - 1}))
+        print(f"{w.name}: pulse DM {pulse_dm:.2f} (trial {trial}), t0 {t0}", flush=True)
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    with fdd.Batch(plans) as b:
+        ys = b.execute(xd)
+        print(json.dumps(b.describe()["classes"]), flush=True)
+        for (w, pulse_dm, t0), x, y, r in zip(beams, xs, ys, rows):
+            yr = y[r].cpu().numpy()
+            ref = O.fdd(x, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, mode="exact", rows=r)
+            err = rel_err(yr, ref)
+            print(f"{w.name} rows {r}: rel err {err}", flush=True)
+            assert err.max() <= TOL
+            peak = int(torch.argmax(y[:, t0 - 2:t0 + 3].amax(dim=1)).item())
+            assert abs(w.dms[peak] - pulse_dm) <= 2.0 * (w.dms[1] - w.dms[0]) + 1.0
+
+
+def test_batch_rejections():
+    w = W.small_fp32()
+    lib = fdd.library()
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Batch([])
+    assert e.value.status == 1
+    with plan_of(w, "exact", "fp32", False) as p:
+        d = fdd.BatchDesc()
+        d.flags = 1 << 7
+        with pytest.raises(fdd.FddError):
+            fdd.fdd_batch_create([p.handle], d)
+    long = W.tiny_random(7, 4, 1 << 17, 3, 1 << 17, single_chunk=True)
+    with plan_of(long, "exact", "fp32", False) as p:
+        with pytest.raises(fdd.FddError) as e:
+            fdd.Batch([p])
+        assert e.value.status == 3
+    dry = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, single_chunk=True, dry_run=True)
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Batch([dry])
+    assert e.value.status == 1 and "dry-run" in str(e.value)
+    power = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, single_chunk=True,
+                     power_only=True, workspace=False)
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Batch([power])
+    assert e.value.status == 3
+    assert lib.fdd_batch_destroy(None) == 0
