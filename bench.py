@@ -46,6 +46,8 @@ PEAK = {  # MI355X published dense peaks
 METRIC = "DM-trial samples/s (N_DM·N_t/s), FP32 FDD vs FP16-split MFMA at stated err"
 KERNEL_SOURCES = {
     "mfma_f32": "paper_2110_03482_amd/csrc/phasor_mfma_f32.hip",
+    "mfma_f16_split": "paper_2110_03482_amd/csrc/phasor_split.hip",
+    "mfma_bf16_split": "paper_2110_03482_amd/csrc/phasor_split.hip",
     "valu": "paper_2110_03482_amd/csrc/phasor_valu.hip",
 }
 
