@@ -215,7 +215,7 @@ def run_periodicity(args, dev) -> int:
     result = base_result(args, w.n_dm * w.n_samp / (ms * 1e-3), ms, "f32" if prec == "fp32" else "f16x2+f32acc",
                          config)
     result["stages_ms"] = {"forward_fft": stage_ms[1], "phasor_sum_power": stage_ms[2]}
-    result["roofline"] = {"kernel": f"phasor_sum_{plan.kernel}", "bound": "mfma" if plan.kernel.startswith("mfma") else "alu",
+    result["roofline"] = {"kernel": f"phasor_sum_{plan.kernel}", "bound": "alu" if plan.kernel == "valu" else "mfma",
                           "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                           "traffic": None, "algorithmic_flops_per_launch": flops}
     plan.close()
@@ -315,7 +315,7 @@ def main() -> int:
         peak = {"fp32": PEAK["fp32_mfma_TFLOPs"], "fp16_split": PEAK["fp16_mfma_TFLOPs"],
                 "bf16_split": PEAK["bf16_mfma_TFLOPs"]}[form["precision"]]
         wl = w.name + f"_{args.mode}_{form['precision']}"
-        return {"kernel": f"phasor_sum_{form['kernel']}", "bound": "mfma" if form["kernel"].startswith("mfma") else "alu",
+        return {"kernel": f"phasor_sum_{form['kernel']}", "bound": "alu" if form["kernel"] == "valu" else "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(form["kernel"], wl), "algorithmic_flops_per_launch": flops}
 

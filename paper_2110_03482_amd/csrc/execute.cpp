@@ -64,6 +64,11 @@ PhasorArgs phasor_args(fdd_plan_t p) {
   a.n_pow_bins = (int)(p->L / 2);
   a.log_len = p->log_len;
   a.tile_variant = p->tile_variant;
+  if (p->fac_fine > 0) {
+    a.n_coarse = p->fac_coarse;
+    a.n_fine = p->fac_fine;
+    a.vtab = a.ptab + (size_t)p->desc.n_chan * (size_t)p->fac_coarse;
+  }
   return a;
 }
 
@@ -83,7 +88,8 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   a.Yr = (float*)(p->d_ws + p->ws.Yr);
   a.Yi = (float*)(p->d_ws + p->ws.Yi);
   hipError_t e;
-  if (p->kernel == "mfma_f32") e = launch_phasor_mfma_f32(a, st);
+  if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
+  else if (p->kernel == "mfma_f32") e = launch_phasor_mfma_f32(a, st);
   else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
   else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
   else e = launch_phasor_valu(a, st);
@@ -125,7 +131,8 @@ fdd_status fdd_power_spectrum(fdd_plan_t p, const void* in, float* out, void* st
   if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
     a.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
   hipError_t e;
-  if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+  if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
+  else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
   else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
   else e = launch_phasor_valu(a, st);
   if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");

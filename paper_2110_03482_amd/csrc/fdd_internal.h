@@ -64,6 +64,11 @@ struct PhasorArgs {
   float dc_add = 0.0f;              // added to Re Y at bin 0 before power (8-bit zero point)
   int tile_variant = 0;             // matrix-core tile shape (0 = default)
   int n_dmt = 0, n_bb = 0;          // grouped launches: DM tiles and bin blocks of this beam
+  // DM-factorised kernels (uniform DM grid, exact delays): trial a*n_fine + b has the delay
+  // tau_coarse[a] + tau_fine[b]; ptab then holds [n_chan][n_coarse] and vtab [n_chan][n_fine]
+  const uint4* vtab = nullptr;
+  int n_coarse = 0;
+  int n_fine = 0;
 };
 
 // Grouped launch over several beams (the batched form): tiles [prefix[b], prefix[b+1]) belong
@@ -168,6 +173,12 @@ hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st);
 hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st);
 bool phasor_mfma_f32_supported(int n_chunks);
 bool phasor_split_supported(int n_chunks);
+// DM-factorised kernels: fine DMs per coarse row for n_chunks chunks (0 if not supported), and
+// the launch (precision: fdd_precision) of a Y-plane or power-spectrum phasor sum.
+int phasor_fac_fine(int n_chunks);
+hipError_t launch_phasor_fac(const PhasorArgs& a, int precision, hipStream_t st);
+int64_t phasor_fac_tiles(PhasorArgs* a, int precision);
+hipError_t launch_phasor_fac_grouped(int precision, bool persist, const Group<PhasorArgs>& g, hipStream_t st);
 
 // Grouped launches of the batched form.  Tiles per beam (for the prefix sums) come from the
 // *_tiles functions, which also fill a.n_dmt / a.n_bb where the kernel needs them.
@@ -211,6 +222,9 @@ struct fdd_plan_s {
   bool dry_run = false;
   std::string kernel = "valu";
   int tile_variant = 0;                 // FDD_TILE_VARIANT override
+  // DM factorisation (uniform DM grid, exact delays): trial j = a * fac_fine + b
+  int fac_fine = 0, fac_coarse = 0;     // 0: not factorised
+  double fac_dm0 = 0.0, fac_step = 0.0;
   // stage timing: a ring of `prof_depth` calls x 5 events
   int prof_depth = 0;
   int64_t prof_calls = 0;               // calls recorded since the last read

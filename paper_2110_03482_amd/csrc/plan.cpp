@@ -54,13 +54,13 @@ static double kappa_of(double f_mhz, double ref_mhz, double tsamp_s) {
 // (d mod L) << (64 - log2 L) for nearest-sample delays), and the unit phasor of one bin step,
 // exp(+2 pi i inc / 2^64), evaluated in float64.  Channel-major, so that the DM lanes of a
 // kernel read consecutive entries.
-void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) {
-  const size_t nc = p->kappa.size(), nd = p->dms.size();
+static void phase_rows(const fdd_plan_s* p, const double* dms, size_t nd, std::vector<uint4>* out) {
+  const size_t nc = p->kappa.size();
   out->resize(nc * nd);
   const int lg = p->log_len;
   for (size_t c = 0; c < nc; ++c) {
     for (size_t m = 0; m < nd; ++m) {
-      const double tau = p->dms[m] * p->kappa[c];
+      const double tau = dms[m] * p->kappa[c];
       uint32_t hi = 0, lo = 0;
       if (p->desc.delay_mode == FDD_DELAY_ROUND) {
         const double d = std::floor(tau + 0.5);
@@ -87,6 +87,35 @@ void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) {
   }
 }
 
+void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) { phase_rows(p, p->dms.data(), p->dms.size(), out); }
+
+// DM-factorised tables: coarse trials DM_0 + a B dDM (channel-major [n_chan][A]) followed by
+// fine offsets b dDM ([n_chan][B]); the delays of trial a B + b add up to DM_j kappa_c.
+static void factor_tables(const fdd_plan_s* p, std::vector<uint4>* out) {
+  std::vector<double> coarse((size_t)p->fac_coarse), fine((size_t)p->fac_fine);
+  for (int a = 0; a < p->fac_coarse; ++a) coarse[(size_t)a] = p->fac_dm0 + (double)a * p->fac_fine * p->fac_step;
+  for (int b = 0; b < p->fac_fine; ++b) fine[(size_t)b] = (double)b * p->fac_step;
+  std::vector<uint4> tb;
+  phase_rows(p, coarse.data(), coarse.size(), out);
+  phase_rows(p, fine.data(), fine.size(), &tb);
+  out->insert(out->end(), tb.begin(), tb.end());
+}
+
+// A DM list DM_j = DM_0 + j dDM (to 1e-10 of the largest DM), as numpy.linspace makes it.
+static bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step) {
+  const size_t n = dms.size();
+  if (n < 2) return false;
+  *dm0 = dms[0];
+  *step = (dms[n - 1] - dms[0]) / (double)(n - 1);
+  if (!(*step > 0.0)) return false;
+  double big = 0.0;
+  for (double v : dms) big = std::max(big, std::fabs(v));
+  const double tol = 1e-10 * big;
+  for (size_t j = 0; j < n; ++j)
+    if (std::fabs(dms[j] - (*dm0 + (double)j * *step)) > tol) return false;
+  return true;
+}
+
 void twiddle_table(int64_t L, std::vector<float2>* out) {
   out->resize((size_t)L);
   for (int64_t j = 0; j < L; ++j) {
@@ -103,8 +132,9 @@ static fdd_status upload_tables(fdd_plan_s* p) {
   hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), w.tw_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddles)");
   std::vector<uint4> tab;
-  phase_table(p, &tab);
-  e = hipMemcpy(p->d_ws + w.ptab, tab.data(), w.ptab_bytes, hipMemcpyHostToDevice);
+  if (p->fac_fine > 0) factor_tables(p, &tab);
+  else phase_table(p, &tab);
+  e = hipMemcpy(p->d_ws + w.ptab, tab.data(), tab.size() * sizeof(uint4), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase table)");
   return FDD_OK;
 }
@@ -119,7 +149,8 @@ static fdd_status layout(fdd_plan_s* p) {
   };
   w.tw_bytes = (size_t)p->L * sizeof(float2);
   put(&w.tw, w.tw_bytes);
-  if (!mul_ok((size_t)d.n_chan * (size_t)d.n_dm, sizeof(uint4), &w.ptab_bytes))
+  const size_t rows_tab = std::max((size_t)d.n_dm, (size_t)p->fac_coarse + (size_t)p->fac_fine);
+  if (!mul_ok((size_t)d.n_chan * rows_tab, sizeof(uint4), &w.ptab_bytes))
     return fail(FDD_E_NOMEM, "phase table size overflows");
   put(&w.ptab, w.ptab_bytes);
   w.scale_bytes = (size_t)p->n_chunks * sizeof(float);
@@ -271,6 +302,24 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
       return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums support 1 to 24 chunks");
     }
     p->kernel = d.precision == FDD_FP16_SPLIT ? "mfma_f16_split" : "mfma_bf16_split";
+  }
+  // DM factorisation: exact delays on a uniform DM grid, few chunks (where the direct kernels
+  // leave most matrix-core columns empty).  FDD_FACTOR=0 disables it, FDD_FACTOR=all extends
+  // it to every chunk count the factorised kernels take.
+  {
+    const char* fe = std::getenv("FDD_FACTOR");
+    const bool off = fe != nullptr && std::strcmp(fe, "0") == 0;
+    const bool all = fe != nullptr && std::strcmp(fe, "all") == 0;
+    const int fine = phasor_fac_fine((int)p->n_chunks);
+    double dm0 = 0.0, step = 0.0;
+    if (!off && d.delay_mode == FDD_DELAY_EXACT && fine > 0 && (all || p->n_chunks <= 2) &&
+        uniform_grid(p->dms, &dm0, &step)) {
+      p->fac_fine = fine;
+      p->fac_coarse = (d.n_dm + fine - 1) / fine;
+      p->fac_dm0 = dm0;
+      p->fac_step = step;
+      p->kernel = d.precision == FDD_FP32 ? "fac_f32" : d.precision == FDD_FP16_SPLIT ? "fac_f16_split" : "fac_bf16_split";
+    }
   }
   fdd_status st = layout(p);
   if (st != FDD_OK) {

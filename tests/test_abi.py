@@ -141,10 +141,15 @@ def test_null_and_dry_run_execution_rejected():
 
 def test_kernel_selection():
     w = W.small_fp32()
-    assert _dry(w).kernel == "valu"                      # one chunk: matrix-vector shape
+    # one chunk, uniform DMs, exact delays: the DM-factorised matrix-core kernels
+    assert _dry(w).kernel == "fac_f32"
+    assert _dry(w, precision="fp16_split").kernel == "fac_f16_split"
+    assert _dry(w, mode="round").kernel == "valu"        # nearest-sample delays do not factorise
     w2 = W.tiny_random(1, 16, 5000, 8, 1024, False, dm_max=3.0)
-    p = _dry(w2)
+    p = _dry(w2)                                         # random (non-uniform) DMs
     assert p.geometry.n_chunks >= 3 and p.kernel == "mfma_f32"
+    w3 = W.paper_shaped_u8()
+    assert _dry(w3).kernel == "mfma_f32"                 # 21 chunks: direct kernel
 
 
 def test_batch_rejects_without_device_calls():
