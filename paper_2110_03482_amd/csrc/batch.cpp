@@ -35,11 +35,12 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-enum Kind { kValu = 0, kMfmaF32 = 1, kSplitF16 = 2, kSplitBf16 = 3 };
+enum Kind { kValu = 0, kMfmaF32 = 1, kSplitF16 = 2, kSplitBf16 = 3, kFac = 4 };
 
 struct Choice {
   int kind = kValu;
-  int variant = 0;       // matrix-core tile variant, or the chunks per thread of the VALU kernel
+  int variant = 0;       // matrix-core tile variant, chunks per thread of the VALU kernel, or the
+                         // precision of a DM-factorised kernel
   bool persist = false;
   std::string name() const {
     char buf[64];
@@ -47,6 +48,8 @@ struct Choice {
       case kMfmaF32: std::snprintf(buf, sizeof buf, "mfma_f32/v%d/%s", variant, persist ? "persistent" : "grid"); break;
       case kSplitF16: std::snprintf(buf, sizeof buf, "mfma_f16_split/%s", persist ? "persistent" : "grid"); break;
       case kSplitBf16: std::snprintf(buf, sizeof buf, "mfma_bf16_split/%s", persist ? "persistent" : "grid"); break;
+      case kFac: std::snprintf(buf, sizeof buf, "fac_%s/%s", variant == FDD_FP32 ? "f32" : variant == FDD_FP16_SPLIT ? "f16_split" : "bf16_split",
+                               persist ? "persistent" : "grid"); break;
       default: std::snprintf(buf, sizeof buf, "valu/nk%d", variant); break;
     }
     return buf;
@@ -58,6 +61,9 @@ struct Beam {
   int wave = 0;
   int cls = 0;              // phasor shape class
   size_t tab = 0;           // phase table (table arena)
+  size_t ftab = 0;          // DM-factorised tables (table arena), if fine > 0
+  int fine = 0, coarse = 0; // DM factorisation of this beam (0: DM list not uniform, or rounded delays)
+  double dm0 = 0.0, step = 0.0;
   size_t tw = 0;            // twiddles (table arena)
   size_t l1 = 0;            // per-chunk L1 maxima (word index in the small arena), split only
   size_t xt = 0, X = 0, Yr = 0, Yi = 0;   // offsets in the beam's scratch
@@ -171,32 +177,41 @@ const Choice& chosen(const fdd_batch_s* b, const Launch& l) {
   return c.cands[(size_t)c.choice];
 }
 
-// Candidate kernels of the phasor sum for a plan's precision and chunk count.
-Class make_class(const fdd_plan_s* p) {
+// Candidate kernels of the phasor sum for a plan's precision and chunk count; `fac` adds the
+// DM-factorised kernels (uniform DM grid, exact delays).  cands[0] is what fdd_execute runs.
+Class make_class(const fdd_plan_s* p, bool fac) {
   Class c;
   const int N = (int)p->n_chunks;
   c.nt = (2 * N + 15) / 16;
-  char key[96];
+  char key[112];
   const int prec = p->desc.precision;
+  const bool fac_default = p->fac_fine > 0;
+  const char* fs = fac_default ? "+fac0" : fac ? "+fac" : "";
   if (prec == FDD_FP16_SPLIT || prec == FDD_BF16_SPLIT) {
     const int kind = prec == FDD_FP16_SPLIT ? kSplitF16 : kSplitBf16;
-    std::snprintf(key, sizeof key, "%s/L%lld/nt%d", kind == kSplitF16 ? "f16split" : "bf16split",
-                  (long long)p->L, c.nt);
+    std::snprintf(key, sizeof key, "%s/L%lld/nt%d%s", kind == kSplitF16 ? "f16split" : "bf16split",
+                  (long long)p->L, c.nt, fs);
     c.cands.push_back({kind, 0, false});
     c.cands.push_back({kind, 0, true});
   } else if (N == 1) {
-    std::snprintf(key, sizeof key, "fp32/L%lld/n1", (long long)p->L);
+    std::snprintf(key, sizeof key, "fp32/L%lld/n1%s", (long long)p->L, fs);
     c.cands.push_back({kValu, 1, false});
   } else if (N > 24) {
-    std::snprintf(key, sizeof key, "fp32/L%lld/valu", (long long)p->L);
+    std::snprintf(key, sizeof key, "fp32/L%lld/valu%s", (long long)p->L, fs);
     c.cands.push_back({kValu, 4, false});
   } else {
     const bool small = !phasor_mfma_f32_supported(N);   // the single plan keeps these on the VALU
-    std::snprintf(key, sizeof key, "fp32/L%lld/%s%d", (long long)p->L, small ? "n" : "nt", small ? N : c.nt);
+    std::snprintf(key, sizeof key, "fp32/L%lld/%s%d%s", (long long)p->L, small ? "n" : "nt", small ? N : c.nt, fs);
     if (small) c.cands.push_back({kValu, 4, false});
     for (int v = 0; v < kMfmaF32Variants; ++v)
       for (int per = 0; per < 2; ++per) c.cands.push_back({kMfmaF32, v, per == 1});
     if (!small) c.cands.push_back({kValu, 4, false});
+  }
+  if (fac || fac_default) {
+    const Choice g{kFac, prec, false}, q{kFac, prec, true};
+    if (fac_default) c.cands.insert(c.cands.begin(), g);
+    else c.cands.push_back(g);
+    c.cands.push_back(q);
   }
   c.key = key;
   c.ms.assign(c.cands.size(), -1.0f);
@@ -251,7 +266,13 @@ fdd_status fill(fdd_batch_s* b, const void* const* in, float* const* out) {
         a.log_len = p->log_len;
         const Choice& ch = chosen(b, l);
         a.tile_variant = ch.kind == kMfmaF32 ? ch.variant : 0;
-        if (ch.kind == kMfmaF32) tiles = phasor_mfma_f32_tiles(&a, ch.variant);
+        if (ch.kind == kFac) {
+          a.ptab = (const uint4*)(b->d_tab + bm.ftab);
+          a.vtab = a.ptab + (size_t)d.n_chan * (size_t)bm.coarse;
+          a.n_coarse = bm.coarse;
+          a.n_fine = bm.fine;
+          tiles = phasor_fac_tiles(&a, d.precision);
+        } else if (ch.kind == kMfmaF32) tiles = phasor_mfma_f32_tiles(&a, ch.variant);
         else if (ch.kind == kValu) tiles = phasor_valu_tiles(&a, ch.variant);
         else tiles = phasor_split_tiles(&a);
         std::memcpy(b->h_desc.data() + l.args + i * sizeof(PhasorArgs), &a, sizeof a);
@@ -325,6 +346,7 @@ hipError_t enqueue_launch(fdd_batch_s* b, const Launch& l, const void* const* in
         case kMfmaF32: return launch_phasor_mfma_f32_grouped(nt, ch.variant, ch.persist, g, st);
         case kSplitF16: return launch_phasor_split_grouped(false, nt, ch.persist, g, st);
         case kSplitBf16: return launch_phasor_split_grouped(true, nt, ch.persist, g, st);
+        case kFac: return launch_phasor_fac_grouped(ch.variant, ch.persist, g, st);
         default: return launch_phasor_valu_grouped(ch.variant, g, st);
       }
     }
@@ -455,7 +477,12 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
   for (int32_t i = 0; i < n; ++i) {
     Beam& bm = b->beams[(size_t)i];
     bm.plan = plans[i];
-    Class c = make_class(bm.plan);
+    const int fine = phasor_fac_fine((int)bm.plan->n_chunks);
+    if (bm.plan->desc.delay_mode == FDD_DELAY_EXACT && fine > 0 && uniform_grid(bm.plan->dms, &bm.dm0, &bm.step)) {
+      bm.fine = fine;
+      bm.coarse = (bm.plan->desc.n_dm + fine - 1) / fine;
+    }
+    Class c = make_class(bm.plan, bm.fine > 0);
     auto it = class_of.find(c.key);
     if (it == class_of.end()) {
       std::string name;
@@ -496,6 +523,10 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
     bm.tw = it->second;
     bm.tab = off;
     off = align_up(off + (size_t)bm.plan->desc.n_chan * (size_t)bm.plan->desc.n_dm * sizeof(uint4));
+    if (bm.fine > 0) {
+      bm.ftab = off;
+      off = align_up(off + (size_t)bm.plan->desc.n_chan * (size_t)(bm.coarse + bm.fine) * sizeof(uint4));
+    }
   }
   b->tab_bytes = off;
 
@@ -620,6 +651,10 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
       std::vector<uint4> tab;
       phase_table(bm.plan, &tab);
       std::memcpy(tabs.data() + bm.tab, tab.data(), tab.size() * sizeof(uint4));
+      if (bm.fine > 0) {
+        factor_tables(bm.plan, bm.fine, bm.coarse, bm.dm0, bm.step, &tab);
+        std::memcpy(tabs.data() + bm.ftab, tab.data(), tab.size() * sizeof(uint4));
+      }
     }
     hipError_t e = hipMemcpy(b->d_tab, tabs.data(), b->tab_bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) s = hip_fail(e, "hipMemcpy(batch tables)");

@@ -237,6 +237,10 @@ namespace fdd {
 // increments and step phasors of every (channel, DM), channel-major.
 void twiddle_table(int64_t L, std::vector<float2>* out);
 void phase_table(const fdd_plan_s* p, std::vector<uint4>* out);
+// DM factorisation: whether the DM list is DM_0 + j dDM (dDM > 0), and the coarse [n_chan][coarse]
+// plus fine [n_chan][fine] phase tables of trial a * fine + b.
+bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step);
+void factor_tables(const fdd_plan_s* p, int fine, int coarse, double dm0, double step, std::vector<uint4>* out);
 void set_error(const std::string& msg);
 fdd_status fail(fdd_status s, const std::string& msg);
 fdd_status hip_fail(hipError_t e, const char* what);

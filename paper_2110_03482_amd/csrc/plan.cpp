@@ -91,18 +91,18 @@ void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) { phase_rows(p, p
 
 // DM-factorised tables: coarse trials DM_0 + a B dDM (channel-major [n_chan][A]) followed by
 // fine offsets b dDM ([n_chan][B]); the delays of trial a B + b add up to DM_j kappa_c.
-static void factor_tables(const fdd_plan_s* p, std::vector<uint4>* out) {
-  std::vector<double> coarse((size_t)p->fac_coarse), fine((size_t)p->fac_fine);
-  for (int a = 0; a < p->fac_coarse; ++a) coarse[(size_t)a] = p->fac_dm0 + (double)a * p->fac_fine * p->fac_step;
-  for (int b = 0; b < p->fac_fine; ++b) fine[(size_t)b] = (double)b * p->fac_step;
+void factor_tables(const fdd_plan_s* p, int fine, int coarse, double dm0, double step, std::vector<uint4>* out) {
+  std::vector<double> cdm((size_t)coarse), fdm((size_t)fine);
+  for (int a = 0; a < coarse; ++a) cdm[(size_t)a] = dm0 + (double)a * fine * step;
+  for (int b = 0; b < fine; ++b) fdm[(size_t)b] = (double)b * step;
   std::vector<uint4> tb;
-  phase_rows(p, coarse.data(), coarse.size(), out);
-  phase_rows(p, fine.data(), fine.size(), &tb);
+  phase_rows(p, cdm.data(), cdm.size(), out);
+  phase_rows(p, fdm.data(), fdm.size(), &tb);
   out->insert(out->end(), tb.begin(), tb.end());
 }
 
 // A DM list DM_j = DM_0 + j dDM (to 1e-10 of the largest DM), as numpy.linspace makes it.
-static bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step) {
+bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step) {
   const size_t n = dms.size();
   if (n < 2) return false;
   *dm0 = dms[0];
@@ -132,7 +132,7 @@ static fdd_status upload_tables(fdd_plan_s* p) {
   hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), w.tw_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddles)");
   std::vector<uint4> tab;
-  if (p->fac_fine > 0) factor_tables(p, &tab);
+  if (p->fac_fine > 0) factor_tables(p, p->fac_fine, p->fac_coarse, p->fac_dm0, p->fac_step, &tab);
   else phase_table(p, &tab);
   e = hipMemcpy(p->d_ws + w.ptab, tab.data(), tab.size() * sizeof(uint4), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase table)");

@@ -253,3 +253,32 @@ def test_batch_rejections():
         fdd.Batch([power])
     assert e.value.status == 3
     assert lib.fdd_batch_destroy(None) == 0
+
+
+def test_batch_factorised_classes():
+    """Uniform DM grids: the batch offers the DM-factorised kernels; defaults match fdd_execute."""
+    import dataclasses
+    specs = [(24, 4000, 40, 4096, True, "f32", 5.0, "exact"),      # 1 chunk: factorised by default
+             (16, 3000, 20, 2048, False, "f32", 3.0, "exact"),     # 2 chunks: factorised by default
+             (20, 9000, 50, 2048, False, "u8", 4.0, "exact"),      # 5 chunks: direct by default
+             (33, 50000, 65, 4096, False, "f32", 10.0, "exact")]   # 13 chunks: direct by default
+    for precision in ("fp32", "fp16_split"):
+        beams = []
+        for w, x, mode, prec in make_beams(specs, precision, seed0=700):
+            beams.append((dataclasses.replace(w, dms=np.linspace(0.0, float(w.dms[-1]), w.n_dm)), x, mode, prec))
+        xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+        plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+        print(f"factorised classes, {precision}: plan kernels {[p.kernel for p in plans]}", flush=True)
+        with fdd.Batch(plans, autotune=False) as b:
+            ys = [y.cpu().numpy() for y in b.execute(xs)]
+            keys = [c["key"] for c in b.describe()["classes"]]
+        assert any("+fac0" in k for k in keys) and any(k.endswith("+fac") for k in keys), keys
+        singles = single_results(beams, xs)
+        for (w, _, _, _), y, s in zip(beams, ys, singles):
+            assert np.array_equal(y, s), f"{w.name}: batched output differs from fdd_execute"
+        check_oracle(beams, ys, TOL)
+        with fdd.Batch(plans) as b:
+            ys = [y.cpu().numpy() for y in b.execute(xs)]
+            for c in b.describe()["classes"]:
+                print(c["key"], "->", c["choice"], c["candidates"])
+        check_oracle(beams, ys, TOL)
