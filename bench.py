@@ -223,6 +223,42 @@ def run_periodicity(args, dev) -> int:
     return 0
 
 
+def run_crossover(args, dev) -> int:
+    """Run time against the number of trial DMs (the paper's Sec. 4.1 comparison) on the
+    paper-shaped 8-bit input: FDD FP32, FDD FP16 split and brute-force TDD."""
+    import torch
+
+    import paper_2110_03482_amd as fdd
+    import workloads as W
+
+    w0 = W.paper_shaped_u8(0)
+    x = make_paper_input(w0, fdd)
+    xd = torch.from_numpy(x).to(dev)
+    del x
+    rows = []
+    for n_dm in (128, 256, 512, 1024, 2048, 4096):
+        w = W.paper_shaped_u8(0, n_dm=n_dm)
+        out = torch.empty((n_dm, w.n_samp), dtype=torch.float32, device=dev)
+        row = {"n_dm": n_dm}
+        for name, prec, tdd in (("fdd_fp32", "fp32", False), ("fdd_fp16_split", "fp16_split", False), ("tdd", "fp32", True)):
+            plan = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, input="u8",
+                            precision=prec, mode="round" if tdd else args.mode, device=dev, power_only=tdd)
+            fn = (lambda p=plan: p.tdd(xd, out)) if tdd else (lambda p=plan: p.execute(xd, out))
+            ms = timed_steps(fn, args, f"{name} n_dm={n_dm}")
+            row[name] = {"ms": ms, "value": n_dm * w.n_samp / (ms * 1e-3)}
+            plan.close()
+        rows.append(row)
+        del out
+        torch.cuda.empty_cache()
+    main = [r for r in rows if r["n_dm"] == 2048][0]["fdd_fp32"]
+    config = {"workload": f"crossover_paper_u8_1024ch_2p20s_{args.mode}", "n_chan": 1024, "n_samp": 1 << 20,
+              "n_dm": [r["n_dm"] for r in rows], "chunk_len": 1 << 16}
+    result = base_result(args, main["value"], main["ms"], "f32", config)
+    result["crossover"] = rows
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,7 +271,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "periodicity"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "periodicity", "crossover"])
     ap.add_argument("--beams", type=int, default=32, help="batched workload: number of beams")
     ap.add_argument("--tune-cache", default=None, help="batched workload: autotune cache file")
     args = ap.parse_args()
@@ -269,6 +305,8 @@ def main() -> int:
         return run_batched(args, dev)
     if args.workload == "periodicity":
         return run_periodicity(args, dev)
+    if args.workload == "crossover":
+        return run_crossover(args, dev)
     w = W.paper_shaped_u8(0, n_dm=args.n_dm)
     x = make_paper_input(w, fdd)
     xd = torch.from_numpy(x).to(dev)
@@ -305,7 +343,23 @@ def main() -> int:
         torch.cuda.empty_cache()
         return res
 
+    def run_tdd() -> dict:
+        """The time-domain brute-force kernel (Eq. 2) on the same input and DM list."""
+        plan = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, overlap=w.overlap,
+                        single_chunk=w.single_chunk, input=w.input_kind, mode="round", device=dev, power_only=True)
+        out = torch.empty((w.n_dm, w.n_samp), dtype=torch.float32, device=dev)
+        plan.profile(args.steps)
+        ms = timed_steps(lambda: plan.tdd(xd, out), args, "tdd")
+        stage_ms, _ = plan.stage_ms()
+        plan.close()
+        del out
+        torch.cuda.empty_cache()
+        return {"value": samples / (ms * 1e-3), "ms_per_step": ms,
+                "stages_ms": {"transpose": stage_ms[0], "shift_and_sum": stage_ms[2]},
+                "note": "brute-force time-domain dedispersion, nearest-sample delays (the paper's comparison method)"}
+
     forms = [run_form(p) for p in (["fp32", "fp16_split", "bf16_split"] if args.precision == "all" else [args.precision])]
+    tdd_form = run_tdd() if args.precision == "all" else None
     main_form = forms[0]
     g = main_form["geometry"]
     flops = 8.0 * w.n_dm * w.n_chan * g.n_bins * g.n_chunks      # complex MACs of Eq. 7, 8 flops each
@@ -347,6 +401,8 @@ def main() -> int:
                                    "roofline": roofline(f), "rel_err_vs_fp64_oracle": stated_err[f["precision"]]}
                   for f in forms},
     }
+    if tdd_form is not None:
+        result["forms"]["tdd_u8"] = tdd_form
     del xd
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

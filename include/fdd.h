@@ -130,6 +130,14 @@ fdd_status fdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* st
  * |Y[dm, f]|^2 for f = 0 .. L/2-1.  Single-chunk plans only (FDD_E_UNSUPPORTED otherwise). */
 fdd_status fdd_power_spectrum(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
+/* Brute-force time-domain dedispersion (Eq. 2), the method FDD is compared with (Sec. 4.1):
+ *     d_out[dm][t] = sum_c x[c][t + d[dm][c]],   d = floor(tau + 1/2)   (the plan's delays)
+ * with x extended by zeros beyond n_samp, or, in single-chunk plans, zero-padded to chunk_len
+ * and periodic.  Same input and output layouts as fdd_execute; sums of 8-bit input are exact
+ * integers.  Uses the plan's workspace (any plan, power-only included).  FDD_E_UNSUPPORTED if
+ * the delays of 8 consecutive DMs differ by more than 4088 samples in some channel. */
+fdd_status fdd_tdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
+
 /* Release a plan and the workspace it allocated itself (never a caller-owned one). */
 fdd_status fdd_destroy(fdd_plan_t plan);
 

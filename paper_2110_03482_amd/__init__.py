@@ -20,7 +20,7 @@ __all__ = [
     "FDD_BF16_SPLIT", "FDD_DELAY_EXACT", "FDD_DELAY_ROUND", "FDD_PLAN_DRY_RUN",
     "FDD_PLAN_EXTERNAL_WORKSPACE", "FDD_PLAN_POWER_ONLY", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
     "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
-    "fdd_power_spectrum", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
+    "fdd_power_spectrum", "fdd_tdd_execute", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
     "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_kernel", "fdd_status_string",
     "fdd_last_error", "fdd_version", "Plan", "FDD_BATCH_NO_GRAPH", "FDD_BATCH_NO_AUTOTUNE", "BatchDesc",
     "fdd_batch_create", "fdd_batch_execute", "fdd_batch_info", "fdd_batch_describe", "fdd_batch_destroy", "Batch",
@@ -97,6 +97,7 @@ _SIGNATURES = {
     "fdd_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "fdd_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_power_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdd_tdd_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "fdd_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "fdd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
@@ -186,6 +187,11 @@ def fdd_execute(plan, d_in: int, d_out: int, stream: int = 0) -> None:
 def fdd_power_spectrum(plan, d_in: int, d_out: int, stream: int = 0) -> None:
     _check(library().fdd_power_spectrum(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
                                         ctypes.c_void_p(stream)), "fdd_power_spectrum")
+
+
+def fdd_tdd_execute(plan, d_in: int, d_out: int, stream: int = 0) -> None:
+    _check(library().fdd_tdd_execute(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out), ctypes.c_void_p(stream)),
+           "fdd_tdd_execute")
 
 
 def fdd_destroy(plan) -> None:
@@ -341,6 +347,17 @@ class Plan:
         elif out.dtype != torch.float32 or tuple(out.shape) != (self.n_dm, self.n_samp) or not out.is_contiguous():
             raise ValueError("out must be a contiguous float32 tensor [n_dm][n_samp]")
         fdd_execute(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
+        return out
+
+    def tdd(self, x, out=None, stream=None):
+        """Brute-force time-domain dedispersion with the plan's nearest-sample delays, [n_dm][n_samp]."""
+        import torch
+        self._check_input(x)
+        if out is None:
+            out = torch.empty((self.n_dm, self.n_samp), dtype=torch.float32, device=self.device)
+        elif out.dtype != torch.float32 or tuple(out.shape) != (self.n_dm, self.n_samp) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor [n_dm][n_samp]")
+        fdd_tdd_execute(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
         return out
 
     def power_spectrum(self, x, out=None, stream=None):

@@ -116,6 +116,39 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   return FDD_OK;
 }
 
+fdd_status fdd_tdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
+  fdd_status s = check_ready(p, in, out);
+  if (s != FDD_OK) return s;
+  if (p->tdd_span > tdd_span_max())
+    return fail(FDD_E_UNSUPPORTED, "nearest-sample delays of neighbouring DMs differ by " + std::to_string(p->tdd_span) +
+                                       " samples; the time-domain kernel takes at most " + std::to_string(tdd_span_max()));
+  const fdd_plan_desc& d = p->desc;
+  hipStream_t st = (hipStream_t)stream;
+  mark(p, 0, st);
+  TddArgs a;
+  if (d.input == FDD_IN_U8_TIME_MAJOR) {
+    uint8_t* xt = p->d_ws + p->ws.xt;
+    hipError_t e = launch_transpose_u8((const uint8_t*)in, xt, d.n_samp, d.n_chan, st);
+    if (e != hipSuccess) return hip_fail(e, "transpose launch");
+    a.in_u8 = xt;
+  } else {
+    a.in_f32 = (const float*)in;
+  }
+  mark(p, 1, st);
+  mark(p, 2, st);
+  a.out = out;
+  a.dtab = (const int*)(p->d_ws + p->ws.dtab);
+  a.n_samp = d.n_samp;
+  a.period = d.single_chunk ? p->L : 0;
+  a.n_chan = d.n_chan;
+  a.n_dm = d.n_dm;
+  hipError_t e = launch_tdd(a, p->tdd_span, p->tdd_span64, st);
+  if (e != hipSuccess) return hip_fail(e, "time-domain launch");
+  mark(p, 3, st);
+  mark(p, 4, st);
+  return FDD_OK;
+}
+
 fdd_status fdd_power_spectrum(fdd_plan_t p, const void* in, float* out, void* stream) {
   fdd_status s = check_ready(p, in, out);
   if (s != FDD_OK) return s;

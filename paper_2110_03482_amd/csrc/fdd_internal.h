@@ -71,6 +71,18 @@ struct PhasorArgs {
   int n_fine = 0;
 };
 
+// Brute-force time-domain dedispersion (Eq. 2) with nearest-sample delays.
+struct TddArgs {
+  const uint8_t* in_u8 = nullptr;   // channel-major 8-bit input [n_chan][n_samp], or
+  const float* in_f32 = nullptr;    // channel-major float input [n_chan][n_samp]
+  float* out = nullptr;             // [n_dm][n_samp]
+  const int* dtab = nullptr;        // [n_chan][n_dm] delays in samples, floor(tau + 1/2)
+  int64_t n_samp = 0;
+  int64_t period = 0;               // L for single-chunk plans (circular), else 0 (zero extension)
+  int n_chan = 0;
+  int n_dm = 0;
+};
+
 // Grouped launch over several beams (the batched form): tiles [prefix[b], prefix[b+1]) belong
 // to beam b, whose arguments are beams[b].  For the phasor sums each range is a multiple of 8
 // long, so that a tile's beam-local id modulo 8 equals its global id modulo 8.
@@ -162,6 +174,11 @@ inline dim3 grouped_grid(bool persist, const void* kernel, int total) {
 }
 
 hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t st);
+hipError_t launch_tdd(const TddArgs& a, int span, int span64, hipStream_t st);
+int tdd_span_max();    // largest delay spread per channel over a tile of 8 DMs that the kernels take
+int tdd_span64_max();  // the same over the larger DM tiles of the 8-bit kernel for fine grids
+int tdd_tile64();      // DMs per tile of that kernel
+int tdd_dm_tile();     // DMs per tile (8)
 hipError_t launch_transpose_u8(const uint8_t* in, uint8_t* out, int64_t n_samp, int n_chan, hipStream_t st);
 hipError_t launch_r2c(int log_n, const FftArgs& a, hipStream_t st);
 hipError_t launch_c2r(int log_n, const FftArgs& a, hipStream_t st);
@@ -205,6 +222,7 @@ struct WorkspaceLayout {
   size_t Yr = 0, Yi = 0, Y_bytes = 0; // float planes [n_dm][n_chunks][pitch] each (not for power-only plans)
   size_t Z = 0, Z_bytes = 0;          // long transforms: float2 [max(n_chan, n_dm) * n_chunks][L/2]
   size_t l1 = 0, l1_bytes = 0;        // long transforms: per-series L1 sums
+  size_t dtab = 0, dtab_bytes = 0;    // int [n_chan][n_dm] nearest-sample delays (time-domain path)
   size_t total = 0;
 };
 
@@ -224,6 +242,8 @@ struct fdd_plan_s {
   int tile_variant = 0;                 // FDD_TILE_VARIANT override
   // DM factorisation (uniform DM grid, exact delays): trial j = a * fac_fine + b
   int fac_fine = 0, fac_coarse = 0;     // 0: not factorised
+  int tdd_span = 0;                     // largest delay spread over 8 consecutive DMs (time-domain kernel)
+  int tdd_span64 = 0;                   // ... over tdd_tile64() consecutive DMs
   double fac_dm0 = 0.0, fac_step = 0.0;
   // stage timing: a ring of `prof_depth` calls x 5 events
   int prof_depth = 0;

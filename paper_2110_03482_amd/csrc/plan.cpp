@@ -125,6 +125,14 @@ void twiddle_table(int64_t L, std::vector<float2>* out) {
   }
 }
 
+// Nearest-sample delays d = floor(tau + 1/2) of every (channel, DM), channel-major.
+static void delay_table(const fdd_plan_s* p, std::vector<int>* out) {
+  const size_t nc = p->kappa.size(), nd = p->dms.size();
+  out->resize(nc * nd);
+  for (size_t c = 0; c < nc; ++c)
+    for (size_t m = 0; m < nd; ++m) (*out)[c * nd + m] = (int)std::floor(p->dms[m] * p->kappa[c] + 0.5);
+}
+
 static fdd_status upload_tables(fdd_plan_s* p) {
   const WorkspaceLayout& w = p->ws;
   std::vector<float2> tw;
@@ -136,6 +144,10 @@ static fdd_status upload_tables(fdd_plan_s* p) {
   else phase_table(p, &tab);
   e = hipMemcpy(p->d_ws + w.ptab, tab.data(), tab.size() * sizeof(uint4), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase table)");
+  std::vector<int> dt;
+  delay_table(p, &dt);
+  e = hipMemcpy(p->d_ws + w.dtab, dt.data(), w.dtab_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(delay table)");
   return FDD_OK;
 }
 
@@ -182,6 +194,9 @@ static fdd_status layout(fdd_plan_s* p) {
     w.l1_bytes = (size_t)d.n_chan * (size_t)p->n_chunks * sizeof(float);
     put(&w.l1, w.l1_bytes);
   }
+  if (!mul_ok((size_t)d.n_chan * (size_t)d.n_dm, sizeof(int), &w.dtab_bytes))
+    return fail(FDD_E_NOMEM, "delay table size overflows");
+  put(&w.dtab, w.dtab_bytes);
   w.total = off;
   return FDD_OK;
 }
@@ -320,6 +335,21 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
       p->fac_step = step;
       p->kernel = d.precision == FDD_FP32 ? "fac_f32" : d.precision == FDD_FP16_SPLIT ? "fac_f16_split" : "fac_bf16_split";
     }
+  }
+  // spread of the nearest-sample delays over the DM tiles of the time-domain kernels
+  for (int tile : {tdd_dm_tile(), tdd_tile64()}) {
+    int span = 0;
+    for (int32_t c = 0; c < d.n_chan; ++c)
+      for (int32_t m0 = 0; m0 < d.n_dm; m0 += tile) {
+        double lo = 1e300, hi = -1e300;
+        for (int32_t m = m0; m < std::min(d.n_dm, m0 + tile); ++m) {
+          const double dd = std::floor(p->dms[(size_t)m] * p->kappa[(size_t)c] + 0.5);
+          lo = std::min(lo, dd);
+          hi = std::max(hi, dd);
+        }
+        span = std::max(span, (int)std::min(hi - lo, 2e9));
+      }
+    (tile == tdd_dm_tile() ? p->tdd_span : p->tdd_span64) = span;
   }
   fdd_status st = layout(p);
   if (st != FDD_OK) {
