@@ -259,6 +259,49 @@ def run_crossover(args, dev) -> int:
     return 0
 
 
+def run_multibeam(args, dev) -> int:
+    """Beams of one set-up (Sec. 5 outlook): 16 beams of 512 channels x 2^17 float32 samples,
+    2048 DMs 0..1000, L = 2^16 (3 chunks each), batched with and without phasor sharing."""
+    import torch
+
+    import paper_2110_03482_amd as fdd
+    import workloads as W
+
+    n_beams = 16
+    w = W.Workload("multibeam_512ch_2p17s_2048dm", 512, 1250.0, 1550.0, 1550.0, 64e-6, 1 << 17,
+                   np.linspace(0.0, 1000.0, 2048), 1 << 16, 0, False, "f32", 0)
+    xs = [torch.from_numpy(W.gaussian_f32(w.n_chan, w.n_samp, 100 + i)).to(dev) for i in range(n_beams)]
+    outs = [torch.empty((w.n_dm, w.n_samp), dtype=torch.float32, device=dev) for _ in range(n_beams)]
+    samples = n_beams * w.n_dm * w.n_samp
+    forms = {}
+    precisions = ["fp32", "fp16_split"] if args.precision == "all" else [args.precision]
+    for prec in precisions:
+        for share in (False, True):
+            plans = [fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, input="f32",
+                              precision=prec, mode=args.mode, device=dev, workspace=False) for _ in range(n_beams)]
+            batch = fdd.Batch(plans, share_phasors=share, tune_cache=args.tune_cache)
+            label = f"multibeam {prec} share={share}"
+            batch.execute(xs, outs)
+            torch.cuda.synchronize()
+            ms = timed_steps(lambda: batch.execute(xs, outs), args, label)
+            d = batch.describe()
+            forms[f"{prec}{'_shared' if share else ''}"] = {
+                "value": samples / (ms * 1e-3), "ms_per_step": ms,
+                "stacks": [sk["chunks"] for sk in d["stacks"]],
+                "tuned": {c["key"]: c["choice"] for c in d["classes"]}}
+            batch.close()
+            for p in plans:
+                p.close()
+    main = forms[precisions[0]]
+    config = {"workload": f"multibeam_{n_beams}x_512ch_2p17s_2048dm_{args.mode}", "beams": n_beams, "n_chan": 512,
+              "n_samp": 1 << 17, "n_dm": 2048, "chunk_len": 1 << 16}
+    result = base_result(args, main["value"], main["ms_per_step"], "f32" if precisions[0] == "fp32" else "f16x2+f32acc",
+                         config)
+    result["forms"] = forms
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,7 +314,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "periodicity", "crossover"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "periodicity", "crossover", "multibeam"])
     ap.add_argument("--beams", type=int, default=32, help="batched workload: number of beams")
     ap.add_argument("--tune-cache", default=None, help="batched workload: autotune cache file")
     args = ap.parse_args()
@@ -307,6 +350,8 @@ def main() -> int:
         return run_periodicity(args, dev)
     if args.workload == "crossover":
         return run_crossover(args, dev)
+    if args.workload == "multibeam":
+        return run_multibeam(args, dev)
     w = W.paper_shaped_u8(0, n_dm=args.n_dm)
     x = make_paper_input(w, fdd)
     xd = torch.from_numpy(x).to(dev)

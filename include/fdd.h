@@ -165,13 +165,18 @@ fdd_status fdd_profile_read(fdd_plan_t plan, float ms[4], int32_t* n_calls);
  * (create the plans with FDD_PLAN_EXTERNAL_WORKSPACE to spare the memory).  The plans must
  * stay alive while the batch exists.  Beams whose scratch (Fourier-domain input and output)
  * does not fit `scratch_limit` together run in successive waves that reuse one arena.
- * Results equal fdd_execute of each plan to float32 rounding; with FDD_BATCH_NO_AUTOTUNE the
- * batch uses the kernels fdd_execute would use and the results are bitwise identical.
+ * Results equal fdd_execute of each plan to float32 rounding; with FDD_BATCH_NO_AUTOTUNE and
+ * without FDD_BATCH_SHARE_PHASORS the batch uses the kernels fdd_execute would use and the
+ * results are bitwise identical.
  * ------------------------------------------------------------------------------------------ */
 typedef struct fdd_batch_s* fdd_batch_t;
 
-#define FDD_BATCH_NO_GRAPH 1u     /* enqueue the grouped launches directly (no graph capture) */
-#define FDD_BATCH_NO_AUTOTUNE 2u  /* use the single-plan kernel choice for every class */
+#define FDD_BATCH_NO_GRAPH 1u       /* enqueue the grouped launches directly (no graph capture) */
+#define FDD_BATCH_NO_AUTOTUNE 2u    /* use the single-plan kernel choice for every class */
+#define FDD_BATCH_SHARE_PHASORS 4u  /* stack beams of one set-up (channels, DMs, sampling, FFT length,
+                                       overlap, precision, delay mode) along the chunk axis, up to
+                                       24 chunks per stack, so that every phasor serves all of them
+                                       (Sec. 5 outlook); the kernel choice then follows the stack */
 
 typedef struct {
   uint32_t flags;          /* FDD_BATCH_* */

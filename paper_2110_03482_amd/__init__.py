@@ -22,7 +22,7 @@ __all__ = [
     "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
     "fdd_power_spectrum", "fdd_tdd_execute", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
     "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_kernel", "fdd_status_string",
-    "fdd_last_error", "fdd_version", "Plan", "FDD_BATCH_NO_GRAPH", "FDD_BATCH_NO_AUTOTUNE", "BatchDesc",
+    "fdd_last_error", "fdd_version", "Plan", "FDD_BATCH_NO_GRAPH", "FDD_BATCH_NO_AUTOTUNE", "FDD_BATCH_SHARE_PHASORS", "BatchDesc",
     "fdd_batch_create", "fdd_batch_execute", "fdd_batch_info", "fdd_batch_describe", "fdd_batch_destroy", "Batch",
 ]
 
@@ -31,7 +31,7 @@ FDD_IN_U8_TIME_MAJOR, FDD_IN_F32_CHAN_MAJOR = 0, 1
 FDD_FP32, FDD_FP16_SPLIT, FDD_BF16_SPLIT = 0, 1, 2
 FDD_DELAY_EXACT, FDD_DELAY_ROUND = 0, 1
 FDD_PLAN_DRY_RUN, FDD_PLAN_EXTERNAL_WORKSPACE, FDD_PLAN_POWER_ONLY = 1, 2, 4
-FDD_BATCH_NO_GRAPH, FDD_BATCH_NO_AUTOTUNE = 1, 2
+FDD_BATCH_NO_GRAPH, FDD_BATCH_NO_AUTOTUNE, FDD_BATCH_SHARE_PHASORS = 1, 2, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # FDD_LIBRARY overrides the in-tree build (e.g. to compare two builds of the library)
@@ -408,10 +408,11 @@ class Batch:
     """
 
     def __init__(self, plans: Sequence[Plan], graph: bool = True, autotune: bool = True, scratch_limit: int = 0,
-                 tune_cache: Optional[str] = None):
+                 tune_cache: Optional[str] = None, share_phasors: bool = False):
         self.plans = list(plans)
         d = BatchDesc()
-        d.flags = (0 if graph else FDD_BATCH_NO_GRAPH) | (0 if autotune else FDD_BATCH_NO_AUTOTUNE)
+        d.flags = ((0 if graph else FDD_BATCH_NO_GRAPH) | (0 if autotune else FDD_BATCH_NO_AUTOTUNE) |
+                   (FDD_BATCH_SHARE_PHASORS if share_phasors else 0))
         d.reserved = 0
         d.scratch_limit = int(scratch_limit)
         self._cache = tune_cache.encode() if tune_cache else None

@@ -9,7 +9,11 @@
 //   grouped phasor sum per shape class -> grouped C2R per FFT length]
 //
 // Grouped kernels find their beam from a prefix sum over per-beam tile counts, so beams of
-// any n_chan / n_samp / n_dm share a launch.  The phasor sum of every shape class (precision,
+// any n_chan / n_samp / n_dm share a launch.  With FDD_BATCH_SHARE_PHASORS, beams observed with
+// one set-up (same channels, DMs, sampling, FFT length and overlap) are stacked along the chunk
+// axis into one phasor-sum problem: every phasor then serves the chunks of all of them (the
+// Sec. 5 outlook of reusing phase rotations across beams), and single-chunk beams become
+// matrix products with one column pair per beam.  The phasor sum of every shape class (precision,
 // FFT length, chunk-column tiles) has several candidate kernels: the matrix-core tile shapes,
 // one-workgroup-per-tile or persistent launches, and the vector-ALU kernel.  The autotuner
 // times each candidate on the batch's own data on the first call and keeps the fastest, in
@@ -58,17 +62,27 @@ struct Choice {
 
 struct Beam {
   fdd_plan_t plan = nullptr;
+  int stack = 0;            // the phasor-sum problem this beam's chunks belong to
+  int koff = 0;             // first chunk of this beam in its stack
+  size_t xt = 0;            // transposed 8-bit input, offset in the stack's scratch
+};
+
+// One phasor-sum problem: a beam, or beams sharing a set-up stacked along the chunk axis.
+struct Stack {
+  std::vector<int> beams;
+  const fdd_plan_s* rep = nullptr;   // a member plan (the set-up they share)
+  int n_chunks = 0;                  // chunks of all members (matrix-core column pairs)
   int wave = 0;
-  int cls = 0;              // phasor shape class
-  size_t tab = 0;           // phase table (table arena)
-  size_t ftab = 0;          // DM-factorised tables (table arena), if fine > 0
-  int fine = 0, coarse = 0; // DM factorisation of this beam (0: DM list not uniform, or rounded delays)
+  int cls = 0;                       // phasor shape class
+  size_t tab = 0;                    // phase table (table arena)
+  size_t ftab = 0;                   // DM-factorised tables (table arena), if fine > 0
+  int fine = 0, coarse = 0;          // DM factorisation (0: DM list not uniform, or rounded delays)
   double dm0 = 0.0, step = 0.0;
-  size_t tw = 0;            // twiddles (table arena)
-  size_t l1 = 0;            // per-chunk L1 maxima (word index in the small arena), split only
-  size_t xt = 0, X = 0, Yr = 0, Yi = 0;   // offsets in the beam's scratch
-  size_t scratch = 0;                      // base of the beam's scratch in the arena
-  size_t bytes = 0;                        // size of the beam's scratch
+  size_t tw = 0;                     // twiddles (table arena)
+  size_t l1 = 0;                     // per-chunk L1 maxima (word index in the small arena), split only
+  size_t X = 0, Yr = 0, Yi = 0;      // offsets in the stack's scratch
+  size_t scratch = 0;                // base of the stack's scratch in the arena
+  size_t bytes = 0;                  // size of the stack's scratch
 };
 
 struct Class {
@@ -88,7 +102,7 @@ struct Launch {
   int log_n = 0;              // FFT stages: log2(L / 2)
   bool u8 = false;
   int cls = -1;               // phasor stage
-  std::vector<int> beams;
+  std::vector<int> beams;     // beams (transpose, FFT stages) or stacks (phasor stage)
   size_t args = 0, prefix = 0;   // descriptor buffer offsets
   size_t ctr = 0;             // phasor stage: word index of its 8 ticket counters
   int total = 0;
@@ -138,6 +152,7 @@ bool save_cache_file(const std::string& path, const std::map<std::string, std::s
 
 struct fdd_batch_s {
   std::vector<Beam> beams;
+  std::vector<Stack> stacks;
   std::vector<Class> classes;
   std::vector<Launch> launches;
   int n_waves = 0;
@@ -179,13 +194,11 @@ const Choice& chosen(const fdd_batch_s* b, const Launch& l) {
 
 // Candidate kernels of the phasor sum for a plan's precision and chunk count; `fac` adds the
 // DM-factorised kernels (uniform DM grid, exact delays).  cands[0] is what fdd_execute runs.
-Class make_class(const fdd_plan_s* p, bool fac) {
+Class make_class(const fdd_plan_s* p, int N, bool fac, bool fac_default) {
   Class c;
-  const int N = (int)p->n_chunks;
   c.nt = (2 * N + 15) / 16;
   char key[112];
   const int prec = p->desc.precision;
-  const bool fac_default = p->fac_fine > 0;
   const char* fs = fac_default ? "+fac0" : fac ? "+fac" : "";
   if (prec == FDD_FP16_SPLIT || prec == FDD_BF16_SPLIT) {
     const int kind = prec == FDD_FP16_SPLIT ? kSplitF16 : kSplitBf16;
@@ -219,20 +232,32 @@ Class make_class(const fdd_plan_s* p, bool fac) {
   return c;
 }
 
-// Scratch bytes of one beam: transposed 8-bit input, X, and the two Y planes.
-size_t beam_scratch(const fdd_plan_s* p, Beam* bm) {
-  const fdd_plan_desc& d = p->desc;
+// Scratch bytes of one stack: its members' transposed 8-bit inputs, X and the two Y planes.
+size_t stack_scratch(fdd_batch_s* b, Stack* sk) {
+  const fdd_plan_s* p = sk->rep;
   size_t off = 0;
-  bm->xt = off;
-  if (d.input == FDD_IN_U8_TIME_MAJOR) off = align_up(off + (size_t)d.n_chan * (size_t)d.n_samp);
-  bm->X = off;
-  off = align_up(off + (size_t)d.n_chan * (size_t)p->n_chunks * (size_t)p->pitch * sizeof(float2));
-  bm->Yr = off;
-  const size_t yb = (size_t)d.n_dm * (size_t)p->n_chunks * (size_t)p->pitch * sizeof(float);
+  for (int i : sk->beams) {
+    Beam& bm = b->beams[(size_t)i];
+    const fdd_plan_desc& d = bm.plan->desc;
+    bm.xt = off;
+    if (d.input == FDD_IN_U8_TIME_MAJOR) off = align_up(off + (size_t)d.n_chan * (size_t)d.n_samp);
+  }
+  sk->X = off;
+  off = align_up(off + (size_t)p->desc.n_chan * (size_t)sk->n_chunks * (size_t)p->pitch * sizeof(float2));
+  sk->Yr = off;
+  const size_t yb = (size_t)p->desc.n_dm * (size_t)sk->n_chunks * (size_t)p->pitch * sizeof(float);
   off = align_up(off + yb);
-  bm->Yi = off;
+  sk->Yi = off;
   off = align_up(off + yb);
   return off;
+}
+
+// Whether two plans share a set-up, so that their chunks can share phasors.
+bool same_setup(const fdd_plan_s* x, const fdd_plan_s* y) {
+  const fdd_plan_desc &a = x->desc, &c = y->desc;
+  return a.n_chan == c.n_chan && a.n_dm == c.n_dm && a.ref_freq_mhz == c.ref_freq_mhz && a.tsamp_s == c.tsamp_s &&
+         x->L == y->L && x->S == y->S && a.single_chunk == c.single_chunk && a.precision == c.precision &&
+         a.delay_mode == c.delay_mode && x->freqs == y->freqs && x->dms == y->dms;
 }
 
 // Host copy of the launch descriptors for the given pointers and the current choices.
@@ -243,23 +268,22 @@ fdd_status fill(fdd_batch_s* b, const void* const* in, float* const* out) {
     int64_t acc = 0;
     int* prefix = (int*)(b->h_desc.data() + l.prefix);
     for (size_t i = 0; i < l.beams.size(); ++i) {
-      const Beam& bm = b->beams[(size_t)l.beams[i]];
-      const fdd_plan_s* p = bm.plan;
-      const fdd_plan_desc& d = p->desc;
-      uint8_t* scr = b->d_scr + bm.scratch;
-      const bool split = d.precision != FDD_FP32;
       prefix[i] = (int)acc;
       int64_t tiles = 0;
       if (l.stage == kPhasor) {
+        const Stack& sk = b->stacks[(size_t)l.beams[i]];
+        const fdd_plan_s* p = sk.rep;
+        const fdd_plan_desc& d = p->desc;
+        uint8_t* scr = b->d_scr + sk.scratch;
         PhasorArgs a;
-        a.X = (const float2*)(scr + bm.X);
-        a.Yr = (float*)(scr + bm.Yr);
-        a.Yi = (float*)(scr + bm.Yi);
-        a.ptab = (const uint4*)(b->d_tab + bm.tab);
-        a.l1max = split ? b->d_small + bm.l1 : nullptr;
+        a.X = (const float2*)(scr + sk.X);
+        a.Yr = (float*)(scr + sk.Yr);
+        a.Yi = (float*)(scr + sk.Yi);
+        a.ptab = (const uint4*)(b->d_tab + sk.tab);
+        a.l1max = d.precision != FDD_FP32 ? b->d_small + sk.l1 : nullptr;
         a.n_dm = d.n_dm;
         a.n_chan = d.n_chan;
-        a.n_chunks = (int)p->n_chunks;
+        a.n_chunks = sk.n_chunks;
         a.pitch = p->pitch;
         a.n_bins = (int)p->n_bins;
         a.n_pow_bins = (int)(p->L / 2);
@@ -267,32 +291,38 @@ fdd_status fill(fdd_batch_s* b, const void* const* in, float* const* out) {
         const Choice& ch = chosen(b, l);
         a.tile_variant = ch.kind == kMfmaF32 ? ch.variant : 0;
         if (ch.kind == kFac) {
-          a.ptab = (const uint4*)(b->d_tab + bm.ftab);
-          a.vtab = a.ptab + (size_t)d.n_chan * (size_t)bm.coarse;
-          a.n_coarse = bm.coarse;
-          a.n_fine = bm.fine;
+          a.ptab = (const uint4*)(b->d_tab + sk.ftab);
+          a.vtab = a.ptab + (size_t)d.n_chan * (size_t)sk.coarse;
+          a.n_coarse = sk.coarse;
+          a.n_fine = sk.fine;
           tiles = phasor_fac_tiles(&a, d.precision);
         } else if (ch.kind == kMfmaF32) tiles = phasor_mfma_f32_tiles(&a, ch.variant);
         else if (ch.kind == kValu) tiles = phasor_valu_tiles(&a, ch.variant);
         else tiles = phasor_split_tiles(&a);
         std::memcpy(b->h_desc.data() + l.args + i * sizeof(PhasorArgs), &a, sizeof a);
       } else {
+        const Beam& bm = b->beams[(size_t)l.beams[i]];
+        const Stack& sk = b->stacks[(size_t)bm.stack];
+        const fdd_plan_s* p = bm.plan;
+        const fdd_plan_desc& d = p->desc;
+        uint8_t* scr = b->d_scr + sk.scratch;
         FftArgs f;
-        f.twL = (const float2*)(b->d_tab + bm.tw);
+        f.twL = (const float2*)(b->d_tab + sk.tw);
         f.n_samp = d.n_samp;
         f.stride = p->S;
         f.pitch = p->pitch;
         f.n_chunks = (int)p->n_chunks;
+        f.row_chunks = sk.n_chunks;
         f.log_n = p->log_len - 1;
         if (l.stage == kR2c) {
           if (d.input == FDD_IN_U8_TIME_MAJOR) f.in_u8 = scr + bm.xt;
           else f.in_f32 = (const float*)in[l.beams[i]];
-          f.X = (float2*)(scr + bm.X);
+          f.X = (float2*)(scr + sk.X) + (size_t)bm.koff * (size_t)p->pitch;
           f.n_rows = d.n_chan;
-          f.l1max = split ? b->d_small + bm.l1 : nullptr;
+          f.l1max = d.precision != FDD_FP32 ? b->d_small + sk.l1 + bm.koff : nullptr;
         } else {
-          f.Yr = (const float*)(scr + bm.Yr);
-          f.Yi = (const float*)(scr + bm.Yi);
+          f.Yr = (const float*)(scr + sk.Yr) + (size_t)bm.koff * (size_t)p->pitch;
+          f.Yi = (const float*)(scr + sk.Yi) + (size_t)bm.koff * (size_t)p->pitch;
           f.out = out[l.beams[i]];
           f.keep = d.single_chunk ? d.n_samp : p->S;
           f.n_rows = d.n_dm;
@@ -321,8 +351,8 @@ hipError_t enqueue_launch(fdd_batch_s* b, const Launch& l, const void* const* in
     case kTranspose: {
       const Beam& bm = b->beams[(size_t)l.beams[0]];
       const fdd_plan_desc& d = bm.plan->desc;
-      return launch_transpose_u8((const uint8_t*)in[l.beams[0]], b->d_scr + bm.scratch + bm.xt, d.n_samp, d.n_chan,
-                                 st);
+      return launch_transpose_u8((const uint8_t*)in[l.beams[0]], b->d_scr + b->stacks[(size_t)bm.stack].scratch + bm.xt,
+                                 d.n_samp, d.n_chan, st);
     }
     case kR2c:
     case kC2r: {
@@ -448,7 +478,7 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
   if (n < 1 || plans == nullptr) return fail(FDD_E_INVALID, "a batch needs at least one plan");
   fdd_batch_desc dd{};
   if (desc != nullptr) dd = *desc;
-  if (dd.reserved != 0 || (dd.flags & ~(FDD_BATCH_NO_GRAPH | FDD_BATCH_NO_AUTOTUNE)) != 0)
+  if (dd.reserved != 0 || (dd.flags & ~(FDD_BATCH_NO_GRAPH | FDD_BATCH_NO_AUTOTUNE | FDD_BATCH_SHARE_PHASORS)) != 0)
     return fail(FDD_E_INVALID, "unknown batch flags or nonzero reserved field");
   for (int32_t i = 0; i < n; ++i) {
     const fdd_plan_s* p = plans[i];
@@ -471,18 +501,43 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
   std::map<std::string, std::string> cached;
   if (!b->cache_path.empty()) (void)load_cache_file(b->cache_path, &cached);
 
-  // beams, shape classes (tuning state from the process cache or the file)
+  // beams and stacks: with FDD_BATCH_SHARE_PHASORS, beams of one set-up fill stacks of up to
+  // kMaxStackChunks chunks in order; otherwise every beam is a stack of its own
+  constexpr int kMaxStackChunks = 24;
   b->beams.resize((size_t)n);
-  std::map<std::string, int> class_of;
   for (int32_t i = 0; i < n; ++i) {
     Beam& bm = b->beams[(size_t)i];
     bm.plan = plans[i];
-    const int fine = phasor_fac_fine((int)bm.plan->n_chunks);
-    if (bm.plan->desc.delay_mode == FDD_DELAY_EXACT && fine > 0 && uniform_grid(bm.plan->dms, &bm.dm0, &bm.step)) {
-      bm.fine = fine;
-      bm.coarse = (bm.plan->desc.n_dm + fine - 1) / fine;
+    int target = -1;
+    if (dd.flags & FDD_BATCH_SHARE_PHASORS)
+      for (size_t k = 0; k < b->stacks.size() && target < 0; ++k) {
+        const Stack& sk = b->stacks[k];
+        if (same_setup(sk.rep, bm.plan) && sk.n_chunks + bm.plan->n_chunks <= kMaxStackChunks) target = (int)k;
+      }
+    if (target < 0) {
+      target = (int)b->stacks.size();
+      b->stacks.emplace_back();
+      b->stacks.back().rep = bm.plan;
     }
-    Class c = make_class(bm.plan, bm.fine > 0);
+    Stack& sk = b->stacks[(size_t)target];
+    bm.stack = target;
+    bm.koff = sk.n_chunks;
+    sk.n_chunks += (int)bm.plan->n_chunks;
+    sk.beams.push_back(i);
+  }
+
+  // shape classes of the stacks (tuning state from the process cache or the file)
+  std::map<std::string, int> class_of;
+  for (Stack& sk : b->stacks) {
+    const fdd_plan_s* p = sk.rep;
+    const int fine = phasor_fac_fine(sk.n_chunks);
+    if (p->desc.delay_mode == FDD_DELAY_EXACT && fine > 0 && uniform_grid(p->dms, &sk.dm0, &sk.step)) {
+      sk.fine = fine;
+      sk.coarse = (p->desc.n_dm + fine - 1) / fine;
+    }
+    // the kernel fdd_execute would pick: its own choice for a lone beam, the same rule for a stack
+    const bool fac_default = sk.beams.size() == 1 ? p->fac_fine > 0 : (sk.fine > 0 && sk.n_chunks <= 2);
+    Class c = make_class(p, sk.n_chunks, sk.fine > 0, fac_default);
     auto it = class_of.find(c.key);
     if (it == class_of.end()) {
       std::string name;
@@ -507,35 +562,35 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
       it = class_of.emplace(c.key, (int)b->classes.size()).first;
       b->classes.push_back(c);
     }
-    bm.cls = it->second;
+    sk.cls = it->second;
   }
 
-  // table arena: one twiddle table per FFT length, one phase table per beam
+  // table arena: one twiddle table per FFT length, phase tables per stack
   std::map<int64_t, size_t> tw_of;
   size_t off = 0;
-  for (Beam& bm : b->beams) {
-    const int64_t L = bm.plan->L;
-    auto it = tw_of.find(L);
+  for (Stack& sk : b->stacks) {
+    const fdd_plan_s* p = sk.rep;
+    auto it = tw_of.find(p->L);
     if (it == tw_of.end()) {
-      it = tw_of.emplace(L, off).first;
-      off = align_up(off + (size_t)L * sizeof(float2));
+      it = tw_of.emplace(p->L, off).first;
+      off = align_up(off + (size_t)p->L * sizeof(float2));
     }
-    bm.tw = it->second;
-    bm.tab = off;
-    off = align_up(off + (size_t)bm.plan->desc.n_chan * (size_t)bm.plan->desc.n_dm * sizeof(uint4));
-    if (bm.fine > 0) {
-      bm.ftab = off;
-      off = align_up(off + (size_t)bm.plan->desc.n_chan * (size_t)(bm.coarse + bm.fine) * sizeof(uint4));
+    sk.tw = it->second;
+    sk.tab = off;
+    off = align_up(off + (size_t)p->desc.n_chan * (size_t)p->desc.n_dm * sizeof(uint4));
+    if (sk.fine > 0) {
+      sk.ftab = off;
+      off = align_up(off + (size_t)p->desc.n_chan * (size_t)(sk.coarse + sk.fine) * sizeof(uint4));
     }
   }
   b->tab_bytes = off;
 
-  // memory waves: first-fit decreasing over the beams' scratch sizes
-  std::vector<int> order((size_t)n);
-  for (int32_t i = 0; i < n; ++i) {
+  // memory waves: first-fit decreasing over the stacks' scratch sizes
+  const int ns = (int)b->stacks.size();
+  std::vector<int> order((size_t)ns);
+  for (int i = 0; i < ns; ++i) {
     order[(size_t)i] = i;
-    Beam& bm = b->beams[(size_t)i];
-    bm.bytes = beam_scratch(bm.plan, &bm);
+    b->stacks[(size_t)i].bytes = stack_scratch(b, &b->stacks[(size_t)i]);
   }
   size_t limit = dd.scratch_limit;
   if (limit == 0) {
@@ -548,33 +603,36 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
     limit = free_b / 4 * 3 > b->tab_bytes ? free_b / 4 * 3 - b->tab_bytes : 0;
   }
   std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return b->beams[(size_t)x].bytes > b->beams[(size_t)y].bytes; });
+                   [&](int x, int y) { return b->stacks[(size_t)x].bytes > b->stacks[(size_t)y].bytes; });
   std::vector<size_t> fill_of;
   for (int i : order) {
-    Beam& bm = b->beams[(size_t)i];
-    if (bm.bytes > limit) {
+    Stack& sk = b->stacks[(size_t)i];
+    if (sk.bytes > limit) {
       delete b;
-      return fail(FDD_E_NOMEM, "one beam's scratch (" + std::to_string(bm.bytes) + " bytes) exceeds the scratch limit");
+      return fail(FDD_E_NOMEM, "the scratch of one beam or stack (" + std::to_string(sk.bytes) +
+                                   " bytes) exceeds the scratch limit");
     }
     size_t w = 0;
-    while (w < fill_of.size() && fill_of[w] + bm.bytes > limit) ++w;
+    while (w < fill_of.size() && fill_of[w] + sk.bytes > limit) ++w;
     if (w == fill_of.size()) fill_of.push_back(0);
-    bm.wave = (int)w;
-    bm.scratch = fill_of[w];
-    fill_of[w] += bm.bytes;
+    sk.wave = (int)w;
+    sk.scratch = fill_of[w];
+    fill_of[w] += sk.bytes;
   }
   b->n_waves = (int)fill_of.size();
   b->scr_bytes = *std::max_element(fill_of.begin(), fill_of.end());
 
-  // launches, wave by wave; grouped beams ordered by decreasing work per tile (channels)
+  // launches, wave by wave; grouped items ordered by decreasing work per tile (channels)
   size_t words = 0;
   for (int w = 0; w < b->n_waves; ++w) {
-    std::vector<int> wb;
+    std::vector<int> ws, wb;
     for (int i : order)
-      if (b->beams[(size_t)i].wave == w) wb.push_back(i);
-    std::stable_sort(wb.begin(), wb.end(), [&](int x, int y) {
-      return b->beams[(size_t)x].plan->desc.n_chan > b->beams[(size_t)y].plan->desc.n_chan;
+      if (b->stacks[(size_t)i].wave == w) ws.push_back(i);
+    std::stable_sort(ws.begin(), ws.end(), [&](int x, int y) {
+      return b->stacks[(size_t)x].rep->desc.n_chan > b->stacks[(size_t)y].rep->desc.n_chan;
     });
+    for (int i : ws)
+      for (int j : b->stacks[(size_t)i].beams) wb.push_back(j);
     for (int i : wb)
       if (b->beams[(size_t)i].plan->desc.input == FDD_IN_U8_TIME_MAJOR) {
         Launch l;
@@ -583,15 +641,15 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
         l.beams = {i};
         b->launches.push_back(l);
       }
-    auto grouped = [&](Stage stage, auto key_of) {
+    auto grouped = [&](Stage stage, const std::vector<int>& items, auto key_of) {
       std::map<std::pair<int, int>, std::vector<int>> groups;
-      for (int i : wb) groups[key_of(b->beams[(size_t)i])].push_back(i);
+      for (int i : items) groups[key_of(i)].push_back(i);
       for (auto& g : groups) {
         Launch l;
         l.stage = stage;
         l.wave = w;
         l.beams = g.second;
-        const fdd_plan_s* p = b->beams[(size_t)g.second[0]].plan;
+        const fdd_plan_s* p = stage == kPhasor ? b->stacks[(size_t)g.second[0]].rep : b->beams[(size_t)g.second[0]].plan;
         l.log_n = p->log_len - 1;
         l.u8 = p->desc.input == FDD_IN_U8_TIME_MAJOR;
         if (stage == kPhasor) {
@@ -602,16 +660,17 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
         b->launches.push_back(l);
       }
     };
-    grouped(kR2c, [](const Beam& bm) {
-      return std::make_pair(bm.plan->log_len, bm.plan->desc.input == FDD_IN_U8_TIME_MAJOR ? 1 : 0);
+    grouped(kR2c, wb, [&](int i) {
+      const fdd_plan_s* p = b->beams[(size_t)i].plan;
+      return std::make_pair(p->log_len, p->desc.input == FDD_IN_U8_TIME_MAJOR ? 1 : 0);
     });
-    grouped(kPhasor, [](const Beam& bm) { return std::make_pair(bm.cls, 0); });
-    grouped(kC2r, [](const Beam& bm) { return std::make_pair(bm.plan->log_len, 0); });
+    grouped(kPhasor, ws, [&](int i) { return std::make_pair(b->stacks[(size_t)i].cls, 0); });
+    grouped(kC2r, wb, [&](int i) { return std::make_pair(b->beams[(size_t)i].plan->log_len, 0); });
   }
-  for (Beam& bm : b->beams)
-    if (bm.plan->desc.precision != FDD_FP32) {
-      bm.l1 = words;
-      words += (size_t)bm.plan->n_chunks;
+  for (Stack& sk : b->stacks)
+    if (sk.rep->desc.precision != FDD_FP32) {
+      sk.l1 = words;
+      words += (size_t)sk.n_chunks;
     }
   b->small_words = words;
 
@@ -647,13 +706,13 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
       twiddle_table(kv.first, &tw);
       std::memcpy(tabs.data() + kv.second, tw.data(), tw.size() * sizeof(float2));
     }
-    for (const Beam& bm : b->beams) {
+    for (const Stack& sk : b->stacks) {
       std::vector<uint4> tab;
-      phase_table(bm.plan, &tab);
-      std::memcpy(tabs.data() + bm.tab, tab.data(), tab.size() * sizeof(uint4));
-      if (bm.fine > 0) {
-        factor_tables(bm.plan, bm.fine, bm.coarse, bm.dm0, bm.step, &tab);
-        std::memcpy(tabs.data() + bm.ftab, tab.data(), tab.size() * sizeof(uint4));
+      phase_table(sk.rep, &tab);
+      std::memcpy(tabs.data() + sk.tab, tab.data(), tab.size() * sizeof(uint4));
+      if (sk.fine > 0) {
+        factor_tables(sk.rep, sk.fine, sk.coarse, sk.dm0, sk.step, &tab);
+        std::memcpy(tabs.data() + sk.ftab, tab.data(), tab.size() * sizeof(uint4));
       }
     }
     hipError_t e = hipMemcpy(b->d_tab, tabs.data(), b->tab_bytes, hipMemcpyHostToDevice);
@@ -731,9 +790,17 @@ fdd_status fdd_batch_describe(fdd_batch_t b, char* buf, size_t len, size_t* need
   o << "{\"arch\": \"" << b->arch << "\", \"waves\": " << b->n_waves << ", \"scratch_bytes\": " << b->scr_bytes
     << ", \"table_bytes\": " << b->tab_bytes << ", \"graph\": " << ((b->flags & FDD_BATCH_NO_GRAPH) ? "false" : "true")
     << ",\n \"beams\": [";
-  for (size_t i = 0; i < b->beams.size(); ++i)
-    o << (i ? ", " : "") << "{\"wave\": " << b->beams[i].wave << ", \"class\": " << b->beams[i].cls
-      << ", \"scratch_bytes\": " << b->beams[i].bytes << "}";
+  for (size_t i = 0; i < b->beams.size(); ++i) {
+    const Stack& sk = b->stacks[(size_t)b->beams[i].stack];
+    o << (i ? ", " : "") << "{\"stack\": " << b->beams[i].stack << ", \"first_chunk\": " << b->beams[i].koff
+      << ", \"wave\": " << sk.wave << ", \"class\": " << sk.cls << "}";
+  }
+  o << "],\n \"stacks\": [";
+  for (size_t i = 0; i < b->stacks.size(); ++i) {
+    const Stack& sk = b->stacks[i];
+    o << (i ? ", " : "") << "{\"beams\": " << sk.beams.size() << ", \"chunks\": " << sk.n_chunks
+      << ", \"wave\": " << sk.wave << ", \"class\": " << sk.cls << ", \"scratch_bytes\": " << sk.bytes << "}";
+  }
   o << "],\n \"classes\": [";
   for (size_t c = 0; c < b->classes.size(); ++c) {
     const Class& k = b->classes[c];
@@ -748,7 +815,7 @@ fdd_status fdd_batch_describe(fdd_batch_t b, char* buf, size_t len, size_t* need
   for (size_t i = 0; i < b->launches.size(); ++i) {
     const Launch& l = b->launches[i];
     o << (i ? ", " : "") << "{\"stage\": \"" << names[l.stage] << "\", \"wave\": " << l.wave
-      << ", \"beams\": " << l.beams.size() << ", \"tiles\": " << l.total;
+      << (l.stage == kPhasor ? ", \"stacks\": " : ", \"beams\": ") << l.beams.size() << ", \"tiles\": " << l.total;
     if (l.stage == kPhasor) o << ", \"class\": " << l.cls;
     o << "}";
   }

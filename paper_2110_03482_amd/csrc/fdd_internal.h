@@ -25,6 +25,8 @@ struct FftArgs {
   int64_t pitch = 0;                // bins per row of X / Y
   int n_chunks = 0;
   int n_rows = 0;                   // channels (forward) or DMs (inverse)
+  int row_chunks = 0;               // chunks per row of X / Y when several series share the rows
+                                    // (beams stacked along the chunk axis); 0 = n_chunks
   float add_full = 0.0f;            // constant restored in chunks wholly inside the data
   unsigned int* l1max = nullptr;    // forward: per-chunk max L1 norm (float bits), or null
   int log_n = 0;                    // log2 of the complex points per series (L / 2)

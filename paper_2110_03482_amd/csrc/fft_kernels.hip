@@ -113,7 +113,8 @@ __device__ __forceinline__ void r2c_body(const FftArgs& a, const int k, const in
     if (t == 0) atomicMax(l1max + k, __float_as_uint(s1));   // non-negative floats order as uints
   }
   F::run(v, lds);
-  float2* dst = X + ((int64_t)c * n_chunks + k) * pitch;
+  const int row_chunks = a.row_chunks > 0 ? a.row_chunks : n_chunks;   // chunks per row of X
+  float2* dst = X + ((int64_t)c * row_chunks + k) * pitch;
   F::with_mirror(v, lds, [&](int q, float2 zf, float2 zm) {
     const int f = t + T * q;
     const float2 zc = make_float2(zm.x, -zm.y);                // conj Z[N - f]
@@ -160,7 +161,8 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   const float add_full = a.add_full;
   const float2* __restrict__ twL = a.twL;
   const int t = threadIdx.x;
-  const int64_t row = ((int64_t)dm * n_chunks + k) * pitch;
+  const int row_chunks = a.row_chunks > 0 ? a.row_chunks : n_chunks;   // chunks per row of Y
+  const int64_t row = ((int64_t)dm * row_chunks + k) * pitch;
   const float* yr = Yr + row;
   const float* yi = Yi + row;
   const float scale = 1.0f / (float)N;

@@ -188,7 +188,7 @@ def test_memory_waves():
     with fdd.Batch(plans, autotune=False) as whole:
         ys = [y.cpu().numpy() for y in whole.execute(xs)]
         assert whole.n_waves == 1
-        per_beam = [bm["scratch_bytes"] for bm in whole.describe()["beams"]]
+        per_beam = [sk["scratch_bytes"] for sk in whole.describe()["stacks"]]
     # a limit of the largest beam's scratch forces several waves
     limit = max(per_beam)
     print(f"memory waves: limit {limit} of {sum(per_beam)} bytes", flush=True)
@@ -282,3 +282,36 @@ def test_batch_factorised_classes():
             for c in b.describe()["classes"]:
                 print(c["key"], "->", c["choice"], c["candidates"])
         check_oracle(beams, ys, TOL)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16_split"])
+def test_batch_shared_phasors(precision):
+    """Beams of one set-up stacked along the chunk axis share every phasor (FDD_BATCH_SHARE_PHASORS)."""
+    import dataclasses
+    base = W.tiny_random(900, 24, 3000, 40, 2048, single_chunk=False, input_kind="f32", dm_max=4.0)
+    beams = []
+    for i, (n_samp, kind) in enumerate([(3000, "f32"), (5000, "u8"), (2100, "f32"), (9000, "f32"), (4000, "u8")]):
+        w = dataclasses.replace(base, n_samp=n_samp, input_kind=kind, name=f"shared{i}")
+        x = W.gaussian_u8(n_samp, w.n_chan, 910 + i) if kind == "u8" else W.gaussian_f32(w.n_chan, n_samp, 910 + i)
+        beams.append((w, x, "exact", precision))
+    # one beam of another set-up, and single-chunk beams that stack into a matrix product
+    other = W.tiny_random(901, 17, 3000, 40, 2048, single_chunk=False, input_kind="f32", dm_max=4.0)
+    beams.append((other, W.gaussian_f32(17, 3000, 920), "round", precision))
+    single = W.tiny_random(902, 20, 1500, 33, 2048, single_chunk=True, input_kind="f32", dm_max=6.0)
+    for i in range(3):
+        beams.append((dataclasses.replace(single, name=f"single{i}"), W.gaussian_f32(20, 1500, 930 + i), "exact", precision))
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+    plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+    print(f"shared-phasor batch, {precision}: chunks {[p.geometry.n_chunks for p in plans]}", flush=True)
+    with fdd.Batch(plans, share_phasors=True) as b:
+        ys = [y.cpu().numpy() for y in b.execute(xs)]
+        d = b.describe()
+    print(json.dumps(d["stacks"]), json.dumps(d["classes"]))
+    sizes = sorted(sk["beams"] for sk in d["stacks"])
+    assert sizes == [1, 3, 5], sizes
+    assert len({bm["stack"] for bm in d["beams"][:5]}) == 1
+    singles = single_results(beams, xs)
+    bound = {"fp32": TOL, "fp16_split": TOL}[precision]
+    for (w, _, _, _), y, s1 in zip(beams, ys, singles):
+        assert rel_err(y, s1).max() <= bound, w.name
+    check_oracle(beams, ys, bound)
