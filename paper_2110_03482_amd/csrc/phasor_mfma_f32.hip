@@ -12,7 +12,9 @@
 //  - a workgroup owns 64 DMs (4 waves x 16) and FB = 16 consecutive bins, all chunks;
 //  - channels stream through LDS in groups of KC = 8: the group's data for the 16 bins is
 //    read from HBM once (128-byte runs along f) and rearranged into the two B planes
-//    [c][f][column] (cos-part and sin-part operands);
+//    [c][f][column] (cos-part and sin-part operands), double-buffered: the next group is
+//    deposited into the other buffer right after the current one's products are issued, so
+//    one barrier per group suffices;
 //  - per 4-channel step, lane l generates the phasor of (DM l%16, channel l/16) for the
 //    tile's bins: exact 64-bit phase of the first bin (planner table + sincos_turn), then
 //    complex multiplications by the tabulated step phasor.  Its cos feeds the first MFMA set and its sin the second, so
@@ -51,8 +53,8 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
   constexpr int PLANE = KC * CST;
   // staging elements (float4 = two bins of one (channel, chunk)) per thread, for N <= 8 NT
   constexpr int PER = (KC * 8 * NT * (FB / 2) + 255) / 256;
-  __shared__ float bre[PLANE];
-  __shared__ float bim[PLANE];
+  __shared__ float bre2[2][PLANE];
+  __shared__ float bim2[2][PLANE];
 
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
@@ -67,8 +69,8 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
 
   // zero once: padding columns (>= 2N) are never written by the staging below
   for (int i = tid; i < PLANE; i += 256) {
-    bre[i] = 0.0f;
-    bim[i] = 0.0f;
+    bre2[0][i] = bre2[1][i] = 0.0f;
+    bim2[0][i] = bim2[1][i] = 0.0f;
   }
 
   // Staging map, fixed for all channel blocks: element e = tid + 256 j is the float4 of bins
@@ -94,7 +96,7 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
       if (ccl[j] < KC && cb + ccl[j] < a.n_chan) pf[j] = *(const float4*)(base + goff[j]);
     }
   };
-  auto deposit = [&]() {
+  auto deposit = [&](float* bre, float* bim) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       if (ccl[j] >= KC) continue;
@@ -129,10 +131,13 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
       for (int nt = 0; nt < NT; ++nt) acc[m][f][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
   fetch(0);
-  for (int cb = 0; cb < a.n_chan; cb += KC) {
-    __syncthreads();                          // the previous block's operands are consumed
-    deposit();
-    __syncthreads();
+  __syncthreads();                            // padding zeroed
+  deposit(bre2[0], bim2[0]);
+  __syncthreads();
+  int it = 0;
+  for (int cb = 0; cb < a.n_chan; cb += KC, ++it) {
+    const float* bre = bre2[it & 1];
+    const float* bim = bim2[it & 1];
     if (cb + KC < a.n_chan) fetch(cb + KC);   // in flight while this block computes
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
@@ -165,6 +170,9 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
             acc[m][f][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wi[f], pi[f * NCOL + 16 * nt], acc[m][f][nt], 0, 0, 0);
       }
     }
+    // the other buffer was last read in the previous group, which every wave has left
+    if (cb + KC < a.n_chan) deposit(bre2[(it + 1) & 1], bim2[(it + 1) & 1]);
+    __syncthreads();
   }
 
   // D[i][j] of a 16x16 tile sits in lane 16*(i/4) + j, register i%4.
