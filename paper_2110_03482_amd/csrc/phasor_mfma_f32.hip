@@ -135,22 +135,40 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
   deposit(bre2[0], bim2[0]);
   __syncthreads();
   int it = 0;
+  // phase-table entries of the lane's (DM, channel) seeds, loaded one group ahead
+  uint4 tn[KC / 4][MW];
+#pragma unroll
+  for (int s = 0; s < KC / 4; ++s) {
+    int c = 4 * s + cq;
+    if (c >= a.n_chan) c = a.n_chan - 1;
+#pragma unroll
+    for (int m = 0; m < MW; ++m) tn[s][m] = a.ptab[(int64_t)c * a.n_dm + dmi[m]];
+  }
   for (int cb = 0; cb < a.n_chan; cb += KC, ++it) {
     const float* bre = bre2[it & 1];
     const float* bim = bim2[it & 1];
+    uint4 tc[KC / 4][MW];
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s)
+#pragma unroll
+      for (int m = 0; m < MW; ++m) tc[s][m] = tn[s][m];
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      int c = cb + KC + 4 * s + cq;
+      if (c >= a.n_chan) c = a.n_chan - 1;
+#pragma unroll
+      for (int m = 0; m < MW; ++m) tn[s][m] = a.ptab[(int64_t)c * a.n_dm + dmi[m]];
+    }
     if (cb + KC < a.n_chan) fetch(cb + KC);   // in flight while this block computes
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
-      const int cl = 4 * s + cq;
-      int c = cb + cl;
-      if (c >= a.n_chan) c = a.n_chan - 1;    // its data were staged as zeros
-      const uint4* trow = a.ptab + (int64_t)c * a.n_dm;
+      const int cl = 4 * s + cq;                // channels past n_chan were staged as zeros
       const float* pr = bre + cl * CST + (lane & 15);
       const float* pi = bim + cl * CST + (lane & 15);
 #pragma unroll
       for (int m = 0; m < MW; ++m) {
         float2 w, step;
-        seed_phasor(trow[dmi[m]], (uint32_t)fb0, &w, &step);
+        seed_phasor(tc[s][m], (uint32_t)fb0, &w, &step);
         float wr[FB], wi[FB];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {

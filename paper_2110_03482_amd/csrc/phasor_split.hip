@@ -173,22 +173,45 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[f][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
+  // Phase-table entries of this lane's DM for the 4 channels it seeds, loaded one stage ahead so
+  // that their latency is spent while the previous stage computes.  With two column tiles the
+  // 16 extra registers would cost a wave of occupancy, so that shape loads them in the stage.
+  constexpr bool kAhead = NT != 2;
+  uint4 tnext[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int c = 4 * cq + q;
+    if (c >= a.n_chan) c = a.n_chan - 1;
+    tnext[q] = a.ptab[(int64_t)c * a.n_dm + dm];
+  }
   __syncthreads();                               // colscale
   fetch(0);
   for (int cb = 0; cb < a.n_chan; cb += KC) {
     __syncthreads();                             // the previous stage's operands are consumed
     deposit();
     __syncthreads();
-    if (cb + KC < a.n_chan) fetch(cb + KC);      // in flight while this stage computes
 
-    // phasors of this lane's DM for channels cb + 4 cq .. + 3
+    // phasors of this lane's DM for channels cb + 4 cq .. + 3 (clamped channels: data staged as zeros)
     float2 w[4], st[4];
+    if constexpr (!kAhead) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int c = cb + 4 * cq + q;
-      if (c >= a.n_chan) c = a.n_chan - 1;       // data staged as zeros
-      seed_phasor(a.ptab[(int64_t)c * a.n_dm + dm], (uint32_t)fb0, &w[q], &st[q]);
+      for (int q = 0; q < 4; ++q) {
+        int c = cb + 4 * cq + q;
+        if (c >= a.n_chan) c = a.n_chan - 1;
+        tnext[q] = a.ptab[(int64_t)c * a.n_dm + dm];
+      }
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) seed_phasor(tnext[q], (uint32_t)fb0, &w[q], &st[q]);
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int c = cb + KC + 4 * cq + q;
+        if (c >= a.n_chan) c = a.n_chan - 1;
+        tnext[q] = a.ptab[(int64_t)c * a.n_dm + dm];
+      }
+    }
+    if (cb + KC < a.n_chan) fetch(cb + KC);      // in flight while this stage computes
     const int rowbase = (lane & 15) * ROWW + 4 * cq;     // words
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
