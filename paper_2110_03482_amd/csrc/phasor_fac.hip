@@ -81,14 +81,18 @@ __device__ __forceinline__ void split_pair(float x, float y, uint32_t* hi, uint3
 __device__ __forceinline__ uint32_t neg_hi(uint32_t w) { return w ^ 0x80000000u; }      // (x, y) -> (x, -y)
 __device__ __forceinline__ uint32_t swap16(uint32_t w) { return (w >> 16) | (w << 16); }  // (x, y) -> (y, x)
 
-// tile -> (bin block, coarse row tile); row tiles of one bin block run back to back on one XCD
+// tile -> (bin block, coarse row tile).  Each XCD takes a contiguous range of bin blocks, in
+// order, and the row tiles of one bin block back to back: neighbouring bin blocks share cache
+// lines of X and of the output rows (a block covers only 16-32 bytes of a row), and on one XCD
+// those partial lines meet in the same L2 instead of going to memory once per block.
 struct TileXY {
   int bb, at;
 };
-__device__ __forceinline__ TileXY fac_tile(int bid, int n_at) {
+__device__ __forceinline__ TileXY fac_tile(int bid, int n_at, int n_bb) {
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
-  return {(slot / n_at) * kXcds + xcd, slot % n_at};
+  const int per_xcd = (n_bb + kXcds - 1) / kXcds;
+  return {xcd * per_xcd + slot / n_at, slot % n_at};
 }
 }  // namespace
 
@@ -106,7 +110,7 @@ __device__ __forceinline__ void phasor_fac_f32_body(const PhasorArgs& a, const i
   __shared__ float bre[PLANE];
   __shared__ float bim[PLANE];
 
-  const TileXY tl = fac_tile(bid, n_at);
+  const TileXY tl = fac_tile(bid, n_at, n_bb);
   if (tl.bb >= n_bb) return;                   // uniform per workgroup, before any barrier
   const int fb0 = tl.bb * FB;
   const int lane = tid & 63;
@@ -278,7 +282,7 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
   __shared__ uint4 llo[PLANEW / 4];
   __shared__ float colscale[32];
 
-  const TileXY tl = fac_tile(bid, n_at);
+  const TileXY tl = fac_tile(bid, n_at, n_bb);
   if (tl.bb >= n_bb) return;
   const int fb0 = tl.bb * FB;
   const int lane = tid & 63;
