@@ -49,6 +49,9 @@ KERNEL_SOURCES = {
     "mfma_f16_split": "paper_2110_03482_amd/csrc/phasor_split.hip",
     "mfma_bf16_split": "paper_2110_03482_amd/csrc/phasor_split.hip",
     "valu": "paper_2110_03482_amd/csrc/phasor_valu.hip",
+    "fac_f32": "paper_2110_03482_amd/csrc/phasor_fac.hip",
+    "fac_f16_split": "paper_2110_03482_amd/csrc/phasor_fac.hip",
+    "fac_bf16_split": "paper_2110_03482_amd/csrc/phasor_fac.hip",
 }
 
 
@@ -217,7 +220,8 @@ def run_periodicity(args, dev) -> int:
     result["stages_ms"] = {"forward_fft": stage_ms[1], "phasor_sum_power": stage_ms[2]}
     result["roofline"] = {"kernel": f"phasor_sum_{plan.kernel}", "bound": "alu" if plan.kernel == "valu" else "mfma",
                           "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                          "traffic": None, "algorithmic_flops_per_launch": flops}
+                          "traffic": measured_traffic(plan.kernel, f"{config['workload']}_{prec}"),
+                          "algorithmic_flops_per_launch": flops}
     plan.close()
     print(json.dumps(result), flush=True)
     return 0

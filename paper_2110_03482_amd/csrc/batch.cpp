@@ -15,7 +15,8 @@
 // Sec. 5 outlook of reusing phase rotations across beams), and single-chunk beams become
 // matrix products with one column pair per beam.  The phasor sum of every shape class (precision,
 // FFT length, chunk-column tiles) has several candidate kernels: the matrix-core tile shapes,
-// one-workgroup-per-tile or persistent launches, and the vector-ALU kernel.  The autotuner
+// one-workgroup-per-tile or persistent launches, and the DM-factorised kernels where the DM
+// grid is uniform (the vector-ALU kernel serves the shapes matrix cores do not).  The autotuner
 // times each candidate on the batch's own data on the first call and keeps the fastest, in
 // memory and optionally in a JSON cache file.  The launch sequence is then captured into one
 // HIP graph that every later call replays with a single launch.
@@ -216,9 +217,9 @@ Class make_class(const fdd_plan_s* p, int N, bool fac, bool fac_default) {
     const bool small = !phasor_mfma_f32_supported(N);   // the single plan keeps these on the VALU
     std::snprintf(key, sizeof key, "fp32/L%lld/%s%d%s", (long long)p->L, small ? "n" : "nt", small ? N : c.nt, fs);
     if (small) c.cands.push_back({kValu, 4, false});
-    for (int v = 0; v < kMfmaF32Variants; ++v)
-      for (int per = 0; per < 2; ++per) c.cands.push_back({kMfmaF32, v, per == 1});
-    if (!small) c.cands.push_back({kValu, 4, false});
+    else
+      for (int v = 0; v < kMfmaF32Variants; ++v)
+        for (int per = 0; per < 2; ++per) c.cands.push_back({kMfmaF32, v, per == 1});
   }
   if (fac || fac_default) {
     const Choice g{kFac, prec, false}, q{kFac, prec, true};
@@ -396,7 +397,11 @@ fdd_status enqueue_all(fdd_batch_s* b, const void* const* in, hipStream_t st) {
 
 // Time every candidate of every unsettled class on the beams of the first wave holding it:
 // the wave's forward stages run once, then each candidate runs once to warm up and is timed
-// (the best of three when a run is shorter than 50 ms).  Synchronises the stream.
+// (the best of three when a run is shorter than 50 ms).  A candidate whose warm-up is already
+// kPrune times slower than the class's best timed run so far keeps its warm-up time and is
+// not timed again.  Synchronises the stream.
+constexpr float kPrune = 1.5f;
+
 fdd_status autotune(fdd_batch_s* b, const void* const* in, float* const* out, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -425,6 +430,7 @@ fdd_status autotune(fdd_batch_s* b, const void* const* in, float* const* out, hi
       if (l.wave != w || l.stage != kPhasor) continue;
       Class& c = b->classes[(size_t)l.cls];
       if (c.settled) continue;
+      float lead = -1.0f;                                  // best timed run of the class so far
       for (size_t k = 0; k < c.cands.size() && s == FDD_OK; ++k) {
         c.choice = (int)k;
         s = fill(b, in, out);
@@ -438,11 +444,18 @@ fdd_status autotune(fdd_batch_s* b, const void* const* in, float* const* out, hi
           if (!check(hipEventSynchronize(e1), "hipEventSynchronize")) break;
           float ms = 0.0f;
           if (!check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) break;
-          if (rep == 0) continue;                          // warm-up
+          if (rep == 0) {                                  // warm-up
+            if (lead > 0.0f && ms > kPrune * lead) {       // clearly slower: keep the warm-up time
+              best = ms;
+              break;
+            }
+            continue;
+          }
           if (best < 0.0f || ms < best) best = ms;
           if (rep == 1 && ms >= 50.0f) break;
         }
         c.ms[k] = best;
+        if (best >= 0.0f && (lead < 0.0f || best < lead)) lead = best;
       }
       if (s != FDD_OK) break;
       int arg = 0;
