@@ -22,6 +22,14 @@
  *    Single-chunk mode zero-pads n_samp to L and is circular over L.
  *  - The inverse drops Im of bins 0 and L/2 and scales by 1/L.  Power spectra keep bins
  *    0 .. L/2-1 and are not normalised.
+ *  - Down-sampled output (Sec. 2.2: where dispersive smearing spans several samples, the
+ *    inverse transform is shortened).  A DM with factor d (a power of two) is inverted with a
+ *    real transform of length M = L/d from bins 0 .. M/2 of Y, scaled by 1/L and with Im of
+ *    bins 0 and M/2 dropped:
+ *        z[dm, kS/d + m] = (1/L) [Re Y_0 + (-1)^m Re Y_{M/2}
+ *                                 + 2 sum_{f=1}^{M/2-1} Re(Y_f exp(2 pi i f m / M))],  m < S/d,
+ *    i.e. the series low-passed to |f| < M/2 (half weight at M/2) and sampled every d-th
+ *    sample; the phasor sum of such a DM only visits bins 0 .. M/2.
  *
  * Memory and streams: every pointer named d_* is device memory owned by the caller.  All
  * device work is enqueued on the given stream (a hipStream_t; NULL = the null stream) and
@@ -90,6 +98,12 @@ typedef struct {
   int32_t precision;            /* fdd_precision */
   int32_t delay_mode;           /* fdd_delay_mode */
   uint32_t flags;               /* FDD_PLAN_* */
+  const int32_t* downsample;    /* host array [n_dm] of output down-sampling factors (powers of
+                                   two, 1 .. chunk_len/64), or NULL for none; copied.  Factors
+                                   above 1 need chunk_len <= 2^16 and a plan that inverts (not
+                                   power-only); in chunked mode the kept stride S becomes a
+                                   multiple of the largest factor (an automatic overlap is
+                                   rounded up; an explicit one must already give that) */
 } fdd_plan_desc;
 
 typedef struct {
@@ -102,6 +116,9 @@ typedef struct {
   double max_delay;         /* max over (dm, c) of tau, samples */
   int64_t n_valid;          /* samples not touched by the end-of-series discard: n_samp - ceil(max tau) */
   size_t workspace_bytes;   /* device bytes a workspace for this plan must hold */
+  int64_t out_samples;      /* float32 samples fdd_execute writes: sum over DMs of ceil(n_samp / d_dm)
+                               (n_dm * n_samp without down-sampling) */
+  int32_t n_segments;       /* runs of consecutive DMs with one down-sampling factor (1 without) */
 } fdd_plan_geometry;
 
 typedef struct fdd_plan_s* fdd_plan_t;
@@ -121,21 +138,29 @@ fdd_status fdd_plan_info(fdd_plan_t plan, fdd_plan_geometry* out);
 fdd_status fdd_set_workspace(fdd_plan_t plan, void* d_workspace, size_t bytes);
 
 /* Dedisperse: d_in is described by the plan's input kind; d_out is float32 [n_dm][n_samp]
- * (DM-major, Sec. 3).  Enqueued on `stream`; does not synchronise.
+ * (DM-major, Sec. 3), or with down-sampling the DM rows one after another, row dm holding
+ * ceil(n_samp / d_dm) samples (offsets from fdd_plan_output_offsets).  Enqueued on `stream`;
+ * does not synchronise.
  * Errors: FDD_E_INVALID (null pointers, dry-run plan), FDD_E_UNSUPPORTED (power-only plan),
  * FDD_E_WORKSPACE, FDD_E_DEVICE. */
 fdd_status fdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
+/* Start of every output row of fdd_execute, in float32 samples from d_out: offsets[dm] for
+ * dm = 0 .. n_dm, offsets[n_dm] = out_samples (host array of n_dm + 1, written by the call). */
+fdd_status fdd_plan_output_offsets(fdd_plan_t plan, int64_t* offsets);
+
 /* Power spectra without the inverse transform (Sec. 5): d_out is float32 [n_dm][L/2],
- * |Y[dm, f]|^2 for f = 0 .. L/2-1.  Single-chunk plans only (FDD_E_UNSUPPORTED otherwise). */
+ * |Y[dm, f]|^2 for f = 0 .. L/2-1 (down-sampling factors do not apply).  Single-chunk plans
+ * only (FDD_E_UNSUPPORTED otherwise). */
 fdd_status fdd_power_spectrum(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
 /* Brute-force time-domain dedispersion (Eq. 2), the method FDD is compared with (Sec. 4.1):
  *     d_out[dm][t] = sum_c x[c][t + d[dm][c]],   d = floor(tau + 1/2)   (the plan's delays)
  * with x extended by zeros beyond n_samp, or, in single-chunk plans, zero-padded to chunk_len
  * and periodic.  Same input and output layouts as fdd_execute; sums of 8-bit input are exact
- * integers.  Uses the plan's workspace (any plan, power-only included).  FDD_E_UNSUPPORTED if
- * the delays of 8 consecutive DMs differ by more than 4088 samples in some channel. */
+ * integers.  Uses the plan's workspace (any plan, power-only included); the output is at full
+ * time resolution whatever the plan's down-sampling factors.  FDD_E_UNSUPPORTED if the delays
+ * of 8 consecutive DMs differ by more than 4088 samples in some channel. */
 fdd_status fdd_tdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
 /* Release a plan and the workspace it allocated itself (never a caller-owned one). */
@@ -187,7 +212,7 @@ typedef struct {
 } fdd_batch_desc;
 
 /* Group `n_plans` plans (host array) into a batch on the current device: validates that every
- * plan can run batched (not dry-run, not power-only, chunk_len <= 2^16), plans the waves,
+ * plan can run batched (not dry-run, not power-only, chunk_len <= 2^16, no down-sampling), plans the waves,
  * allocates the scratch, uploads the tables.
  * Errors: FDD_E_INVALID, FDD_E_UNSUPPORTED, FDD_E_NOMEM, FDD_E_DEVICE. */
 fdd_status fdd_batch_create(int32_t n_plans, const fdd_plan_t* plans, const fdd_batch_desc* desc,
@@ -216,6 +241,14 @@ fdd_status fdd_batch_destroy(fdd_batch_t batch);
 /* tau (samples) of every channel at one DM, Eq. 1, exactly as plans compute it. */
 fdd_status fdd_dispersion_delays(int32_t n_chan, const double* chan_freq_mhz, double ref_freq_mhz,
                                  double tsamp_s, double dm, double* tau_out);
+/* Down-sampling factors from intra-channel smearing (Sec. 2.2: time-domain pipelines
+ * down-sample once the smearing exceeds native samples).  The smearing of a DM is the Eq. 1
+ * delay across the lowest channel, k_DM DM ((nu_lo - w/2)^-2 - (nu_lo + w/2)^-2) / t_samp
+ * samples, with nu_lo the lowest channel frequency and w the smallest spacing of adjacent
+ * channel frequencies (0 for one channel); out[dm] is the largest power of two <= that
+ * smearing, at least 1 and at most max_factor (a power of two >= 1).  Host only. */
+fdd_status fdd_smearing_factors(int32_t n_chan, const double* chan_freq_mhz, double tsamp_s, int32_t n_dm,
+                                const double* dm, int32_t max_factor, int32_t* out);
 /* The plan's float64 delay table tau[n_dm][n_chan] (host copy). */
 fdd_status fdd_plan_delays(fdd_plan_t plan, double* tau_out);
 /* Name of the phasor-sum kernel family a plan selected ("valu", "mfma_f32", ...). */

@@ -33,6 +33,12 @@ Readings where the paper is silent or inconsistent (all listed in the design not
   is circular over L.
 * The inverse transform drops the imaginary parts of bins 0 and L/2 and scales by 1/L.
 * Power spectra keep bins 0 .. L/2 - 1 (DC kept, Nyquist dropped), unnormalised.
+* Down-sampling by a shorter inverse transform (Sec. 2.2): a DM with factor d (a power of two)
+  is inverted with a real transform of length M = L/d over bins 0 .. M/2, Im of bins 0 and
+  M/2 dropped, scaled by 1/L (not 1/M), so that slowly varying series keep their amplitude:
+  the series low-passed to |f| < M/2 (half weight at M/2) and sampled every d-th sample.
+  Chunk k keeps its first S/d samples at output offset kS/d, so S must be a multiple of d;
+  an automatic overlap is rounded up until S is a multiple of the largest factor.
 
 Library primitives used as steps: numpy.fft.rfft / irfft in float64 (pinned against the
 direct DFT definition by the tests).
@@ -61,6 +67,7 @@ __all__ = [
     "explicit_irdft",
     "input_segment",
     "oracle_fdd_rows",
+    "inverse_real_short",
 ]
 
 # Dispersion constant in MHz^2 pc^-1 cm^3 s (Eq. 1).
@@ -91,12 +98,13 @@ def nearest_sample(tau: np.ndarray) -> np.ndarray:
 
 
 def chunk_geometry(n_samp: int, chunk_len: int, overlap: int, single_chunk: bool,
-                   max_tau: float):
+                   max_tau: float, max_factor: int = 1):
     """(stride S, n_chunks, overlap D) of the overlap-save time chunking.
 
     Sec. 2.2: at least the maximum delay must be discarded at the end of every transformed
     series, so D >= ceil(max tau) and S = L - D samples of each chunk are kept.  overlap <= 0
-    picks D = ceil(max tau).  Single-chunk mode transforms one zero-padded series of length L.
+    picks D = ceil(max tau), enlarged until S is a multiple of max_factor (the largest
+    down-sampling factor).  Single-chunk mode transforms one zero-padded series of length L.
     """
     L = int(chunk_len)
     if L <= 0 or (L & (L - 1)) != 0:
@@ -109,9 +117,14 @@ def chunk_geometry(n_samp: int, chunk_len: int, overlap: int, single_chunk: bool
     D = need if overlap <= 0 else int(overlap)
     if D < need:
         raise ValueError("overlap shorter than the maximum delay")
+    if overlap <= 0:
+        while (L - D) % max_factor != 0:
+            D += 1
     S = L - D
     if S <= 0:
         raise ValueError("overlap must be shorter than the chunk")
+    if S % max_factor != 0:
+        raise ValueError("the kept stride must be a multiple of every down-sampling factor")
     return S, -(-int(n_samp) // S), D
 
 
@@ -218,22 +231,35 @@ def inverse_real(Y: np.ndarray, L: int) -> np.ndarray:
     return np.fft.irfft(Yc, n=L, axis=-1)
 
 
+def inverse_real_short(Y: np.ndarray, L: int, d: int) -> np.ndarray:
+    """Down-sampled inverse (Sec. 2.2): real series of length M = L/d from bins 0 .. M/2 of a
+    length-L spectrum, Im of bins 0 and M/2 dropped, scaled by 1/L."""
+    M = L // d
+    return inverse_real(np.asarray(Y)[..., : M // 2 + 1], M) * (M / L)
+
+
 def oracle_fdd_rows(x: np.ndarray, kind: str, tau: np.ndarray, L: int, stride: int,
                     n_chunks: int, single_chunk: bool, mode: str,
-                    rows: Optional[Iterable[int]] = None, power: bool = False) -> np.ndarray:
+                    rows: Optional[Iterable[int]] = None, power: bool = False,
+                    factors: Optional[Sequence[int]] = None):
     """Fourier-domain dedispersion of the requested DM rows (all rows by default).
 
     Returns float64 [len(rows), n_samp] dedispersed series, or with power=True the power
-    spectra [len(rows), L/2] of the single chunk.
+    spectra [len(rows), L/2] of the single chunk.  With `factors` (one down-sampling factor
+    per DM of tau) it returns a list with one float64 series of ceil(n_samp / d) samples per
+    requested row.
     """
     n_samp = x.shape[0] if kind == "u8" else x.shape[1]
     rows = list(range(tau.shape[0])) if rows is None else list(rows)
+    ds = [1] * len(rows) if factors is None else [int(factors[r]) for r in rows]
     if power:
         if not single_chunk:
             raise ValueError("power spectra need single-chunk mode")
         out = np.zeros((len(rows), L // 2), dtype=np.float64)
-    else:
+    elif factors is None:
         out = np.zeros((len(rows), n_samp), dtype=np.float64)
+    else:
+        out = [np.zeros(-(-n_samp // d), dtype=np.float64) for d in ds]
     W = [phasors(tau[r], L, mode) for r in rows]      # the phasors do not depend on the chunk
     keep = n_samp if single_chunk else stride
     for k in range(n_chunks):
@@ -244,21 +270,27 @@ def oracle_fdd_rows(x: np.ndarray, kind: str, tau: np.ndarray, L: int, stride: i
             if power:
                 out[i] = (Y.real ** 2 + Y.imag ** 2)[: L // 2]
                 continue
-            y = inverse_real(Y, L)
-            n = min(keep, n_samp - t0)
-            out[i, t0: t0 + n] = y[:n]
+            d = ds[i]
+            y = inverse_real(Y, L) if d == 1 else inverse_real_short(Y, L, d)
+            if not single_chunk and stride % d != 0:
+                raise ValueError("the kept stride must be a multiple of every down-sampling factor")
+            o0 = t0 // d                                  # output samples of this chunk start here
+            n = min(-(-keep // d), out[i].shape[0] - o0)
+            out[i][o0: o0 + n] = y[:n]
     return out
 
 
 def fdd(x: np.ndarray, kind: str, dms, freqs_mhz, ref_freq_mhz: float, tsamp_s: float,
         chunk_len: int, overlap: int = 0, single_chunk: bool = False, mode: str = "exact",
-        rows: Optional[Iterable[int]] = None) -> np.ndarray:
-    """Fourier-domain dedispersion from the observation description (Eqs. 1, 3-7)."""
+        rows: Optional[Iterable[int]] = None, factors: Optional[Sequence[int]] = None):
+    """Fourier-domain dedispersion from the observation description (Eqs. 1, 3-7), with
+    optional per-DM down-sampling factors (Sec. 2.2)."""
     tau = delays(dms, freqs_mhz, ref_freq_mhz, tsamp_s)
     n_samp = x.shape[0] if kind == "u8" else x.shape[1]
     max_tau = float(tau.max()) if tau.size else 0.0
-    S, n_chunks, _ = chunk_geometry(n_samp, chunk_len, overlap, single_chunk, max_tau)
-    return oracle_fdd_rows(x, kind, tau, chunk_len, S, n_chunks, single_chunk, mode, rows)
+    dmax = 1 if factors is None else int(max(factors))
+    S, n_chunks, _ = chunk_geometry(n_samp, chunk_len, overlap, single_chunk, max_tau, dmax)
+    return oracle_fdd_rows(x, kind, tau, chunk_len, S, n_chunks, single_chunk, mode, rows, factors=factors)
 
 
 def fdd_power(x: np.ndarray, kind: str, dms, freqs_mhz, ref_freq_mhz: float, tsamp_s: float,

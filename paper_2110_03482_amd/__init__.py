@@ -21,7 +21,8 @@ __all__ = [
     "FDD_PLAN_EXTERNAL_WORKSPACE", "FDD_PLAN_POWER_ONLY", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
     "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
     "fdd_power_spectrum", "fdd_tdd_execute", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
-    "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_kernel", "fdd_status_string",
+    "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_output_offsets", "fdd_smearing_factors",
+    "fdd_plan_kernel", "fdd_status_string",
     "fdd_last_error", "fdd_version", "Plan", "FDD_BATCH_NO_GRAPH", "FDD_BATCH_NO_AUTOTUNE", "FDD_BATCH_SHARE_PHASORS", "BatchDesc",
     "fdd_batch_create", "fdd_batch_execute", "fdd_batch_info", "fdd_batch_describe", "fdd_batch_destroy", "Batch",
 ]
@@ -60,6 +61,7 @@ class PlanDesc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("delay_mode", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("downsample", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -74,6 +76,8 @@ class PlanGeometry(ctypes.Structure):
         ("max_delay", ctypes.c_double),
         ("n_valid", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_size_t),
+        ("out_samples", ctypes.c_int64),
+        ("n_segments", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -105,6 +109,10 @@ _SIGNATURES = {
     "fdd_dispersion_delays": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
     "fdd_plan_delays": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "fdd_plan_output_offsets": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "fdd_smearing_factors": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
     "fdd_plan_kernel": (ctypes.c_char_p, [ctypes.c_void_p]),
     "fdd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "fdd_last_error": (ctypes.c_char_p, []),
@@ -224,6 +232,25 @@ def fdd_plan_delays(plan, n_dm: int, n_chan: int) -> np.ndarray:
     return out
 
 
+def fdd_plan_output_offsets(plan, n_dm: int) -> np.ndarray:
+    """Start of every output row of fdd_execute (n_dm + 1 entries, the last = out_samples)."""
+    out = np.empty(n_dm + 1, dtype=np.int64)
+    _check(library().fdd_plan_output_offsets(plan, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+           "fdd_plan_output_offsets")
+    return out
+
+
+def fdd_smearing_factors(freqs_mhz, tsamp_s: float, dms, max_factor: int) -> np.ndarray:
+    """Per-DM down-sampling factors from the smearing across the lowest channel."""
+    f = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
+    d = np.ascontiguousarray(dms, dtype=np.float64)
+    out = np.empty(d.size, dtype=np.int32)
+    _check(library().fdd_smearing_factors(int(f.size), _dptr(f), float(tsamp_s), int(d.size), _dptr(d),
+                                          int(max_factor), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "fdd_smearing_factors")
+    return out
+
+
 def fdd_plan_kernel(plan) -> str:
     return library().fdd_plan_kernel(plan).decode()
 
@@ -276,9 +303,10 @@ class Plan:
     def __init__(self, freqs_mhz, ref_freq_mhz: float, tsamp_s: float, dms, n_samp: int, chunk_len: int,
                  overlap: int = 0, single_chunk: bool = False, input: str = "f32", precision: str = "fp32",
                  mode: str = "exact", device=None, dry_run: bool = False, power_only: bool = False,
-                 workspace: bool = True):
+                 workspace: bool = True, downsample=None):
         self._freqs = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
         self._dms = np.ascontiguousarray(dms, dtype=np.float64)
+        self._ds = None if downsample is None else np.ascontiguousarray(downsample, dtype=np.int32)
         self.n_chan = int(self._freqs.size)
         self.n_dm = int(self._dms.size)
         self.n_samp = int(n_samp)
@@ -299,8 +327,13 @@ class Plan:
         d.precision = _PRECISIONS[precision]
         d.delay_mode = _MODES[mode]
         d.flags = (FDD_PLAN_DRY_RUN if dry_run else FDD_PLAN_EXTERNAL_WORKSPACE) | (FDD_PLAN_POWER_ONLY if power_only else 0)
+        if self._ds is not None:
+            if self._ds.size != self.n_dm:
+                raise ValueError("downsample needs one factor per DM")
+            d.downsample = self._ds.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         self._handle = fdd_plan(d)
         self.geometry = fdd_plan_info(self._handle)
+        self.downsampled = int(self.geometry.out_samples) != self.n_dm * self.n_samp
         self.kernel = fdd_plan_kernel(self._handle)
         self.workspace = None
         self.device = None
@@ -338,14 +371,25 @@ class Plan:
         s = torch.cuda.current_stream() if stream is None else stream
         return int(s.cuda_stream)
 
+    def output_offsets(self) -> np.ndarray:
+        """Start of every DM's output row in the flat output (n_dm + 1 entries)."""
+        return fdd_plan_output_offsets(self._handle, self.n_dm)
+
+    def rows(self, out):
+        """The DM rows of a flat down-sampled output, as views."""
+        off = self.output_offsets()
+        return [out[int(off[j]): int(off[j + 1])] for j in range(self.n_dm)]
+
     def execute(self, x, out=None, stream=None):
-        """Dedispersed series float32 [n_dm][n_samp]."""
+        """Dedispersed series float32 [n_dm][n_samp]; with down-sampling a flat float32
+        [out_samples] holding the DM rows one after another (see rows())."""
         import torch
         self._check_input(x)
+        shape = (int(self.geometry.out_samples),) if self.downsampled else (self.n_dm, self.n_samp)
         if out is None:
-            out = torch.empty((self.n_dm, self.n_samp), dtype=torch.float32, device=self.device)
-        elif out.dtype != torch.float32 or tuple(out.shape) != (self.n_dm, self.n_samp) or not out.is_contiguous():
-            raise ValueError("out must be a contiguous float32 tensor [n_dm][n_samp]")
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        elif out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
         fdd_execute(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
         return out
 

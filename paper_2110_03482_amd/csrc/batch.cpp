@@ -499,6 +499,8 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
     if (p->dry_run) return fail(FDD_E_INVALID, "a dry-run plan cannot be batched");
     if (p->desc.flags & FDD_PLAN_POWER_ONLY) return fail(FDD_E_UNSUPPORTED, "power-only plans cannot be batched");
     if (p->log_len - 1 > kMaxBlockLogN) return fail(FDD_E_UNSUPPORTED, "batched beams need chunk_len <= 2^16");
+    if (p->segs.size() != 1 || p->segs[0].factor != 1)
+      return fail(FDD_E_UNSUPPORTED, "batched beams take no down-sampled output");
   }
   fdd_batch_s* b = new (std::nothrow) fdd_batch_s();
   if (b == nullptr) return fail(FDD_E_NOMEM, "host allocation failed");

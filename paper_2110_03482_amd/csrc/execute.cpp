@@ -1,5 +1,7 @@
 // Stage sequencing of fdd_execute / fdd_power_spectrum (Algorithm 1 without host copies:
 // inputs and outputs are device resident, so there is nothing to overlap with PCIe).
+#include <algorithm>
+
 #include "fdd_internal.h"
 
 using namespace fdd;
@@ -72,6 +74,30 @@ PhasorArgs phasor_args(fdd_plan_t p) {
   return a;
 }
 
+// The phasor-sum arguments of one segment: its block of the phase table, its Y rows, and the
+// bins 0 .. L/(2d) its shortened inverse reads (all bins for power spectra).
+PhasorArgs segment_args(fdd_plan_t p, const PhasorArgs& all, const Segment& sg, bool power) {
+  PhasorArgs a = all;
+  a.ptab = all.ptab + sg.tab;
+  a.n_dm = sg.n;
+  const size_t rows = (size_t)sg.j0 * (size_t)p->n_chunks * (size_t)p->pitch;
+  if (power) {
+    a.P = all.P + (size_t)sg.j0 * (size_t)all.n_pow_bins;
+  } else {
+    a.Yr = all.Yr + rows;
+    a.Yi = all.Yi + rows;
+    a.n_bins = (int)(p->L / sg.factor / 2 + 1);
+  }
+  return a;
+}
+
+// Chunks k whose input samples [kS, kS + L) all lie inside the data.
+int full_chunks(fdd_plan_t p) {
+  const int64_t n = p->desc.n_samp;
+  if (n < p->L) return 0;
+  return (int)std::min<int64_t>((n - p->L) / p->S + 1, p->n_chunks);
+}
+
 }  // namespace
 
 extern "C" {
@@ -84,34 +110,46 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   mark(p, 0, st);
   s = forward(p, in, st);
   if (s != FDD_OK) return s;
-  PhasorArgs a = phasor_args(p);
-  a.Yr = (float*)(p->d_ws + p->ws.Yr);
-  a.Yi = (float*)(p->d_ws + p->ws.Yi);
+  PhasorArgs all = phasor_args(p);
+  all.Yr = (float*)(p->d_ws + p->ws.Yr);
+  all.Yi = (float*)(p->d_ws + p->ws.Yi);
   hipError_t e;
-  if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
-  else if (p->kernel == "mfma_f32") e = launch_phasor_mfma_f32(a, st);
-  else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
-  else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
-  else e = launch_phasor_valu(a, st);
-  if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+  for (const Segment& sg : p->segs) {
+    const PhasorArgs a = segment_args(p, all, sg, false);
+    if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
+    else if (p->kernel == "mfma_f32") e = launch_phasor_mfma_f32(a, st);
+    else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+    else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+    else e = launch_phasor_valu(a, st);
+    if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+  }
   mark(p, 3, st);
-  FftArgs f;
-  f.Yr = a.Yr;
-  f.Yi = a.Yi;
-  f.out = out;
-  f.twL = (const float2*)(p->d_ws + p->ws.tw);
-  f.n_samp = p->desc.n_samp;
-  f.stride = p->S;
-  f.keep = p->desc.single_chunk ? p->desc.n_samp : p->S;
-  f.pitch = p->pitch;
-  f.n_chunks = (int)p->n_chunks;
-  f.n_rows = p->desc.n_dm;
-  f.add_full = p->desc.input == FDD_IN_U8_TIME_MAJOR ? 128.0f * (float)p->desc.n_chan : 0.0f;
-  f.log_n = p->log_len - 1;
-  e = f.log_n > kMaxBlockLogN
-          ? launch_c2r_long(f, (float2*)(p->d_ws + p->ws.Z), (float2*)(p->d_ws + p->ws.Yr), st)
-          : launch_c2r(f.log_n, f, st);
-  if (e != hipSuccess) return hip_fail(e, "inverse FFT launch");
+  for (const Segment& sg : p->segs) {
+    const PhasorArgs a = segment_args(p, all, sg, false);
+    int lg = 0;
+    while ((1 << lg) < sg.factor) ++lg;
+    FftArgs f;
+    f.Yr = a.Yr;
+    f.Yi = a.Yi;
+    f.out = out + sg.out_off;
+    f.twL = (const float2*)(p->d_ws + (sg.factor == 1 ? p->ws.tw : sg.tw));
+    f.n_samp = sg.n_out;
+    f.stride = p->S / sg.factor;
+    f.keep = p->desc.single_chunk ? sg.n_out : p->S / sg.factor;
+    f.pitch = p->pitch;
+    f.n_chunks = (int)p->n_chunks;
+    f.n_rows = sg.n;
+    f.add_full = p->desc.input == FDD_IN_U8_TIME_MAJOR ? 128.0f * (float)p->desc.n_chan : 0.0f;
+    f.log_n = p->log_len - 1 - lg;
+    if (sg.factor > 1) {               // length L/d, scaled by 1/L; zero point by full-length chunks
+      f.inv_n = 2.0f / (float)p->L;
+      f.full_chunks = full_chunks(p);
+    }
+    e = f.log_n > kMaxBlockLogN
+            ? launch_c2r_long(f, (float2*)(p->d_ws + p->ws.Z), (float2*)(p->d_ws + p->ws.Yr), st)
+            : launch_c2r(f.log_n, f, st);
+    if (e != hipSuccess) return hip_fail(e, "inverse FFT launch");
+  }
   mark(p, 4, st);
   return FDD_OK;
 }
@@ -157,18 +195,21 @@ fdd_status fdd_power_spectrum(fdd_plan_t p, const void* in, float* out, void* st
   mark(p, 0, st);
   s = forward(p, in, st);
   if (s != FDD_OK) return s;
-  PhasorArgs a = phasor_args(p);
-  a.P = out;
+  PhasorArgs all = phasor_args(p);
+  all.P = out;
   // the forward transform removed the 8-bit zero point from a chunk filling the whole
   // transform; the removed offset sits in bin 0 only, with phasor 1
   if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
-    a.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
+    all.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
   hipError_t e;
-  if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
-  else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
-  else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
-  else e = launch_phasor_valu(a, st);
-  if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+  for (const Segment& sg : p->segs) {
+    const PhasorArgs a = segment_args(p, all, sg, true);
+    if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
+    else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+    else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+    else e = launch_phasor_valu(a, st);
+    if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+  }
   mark(p, 3, st);
   mark(p, 4, st);
   return FDD_OK;

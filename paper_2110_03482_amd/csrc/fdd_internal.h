@@ -28,6 +28,10 @@ struct FftArgs {
   int row_chunks = 0;               // chunks per row of X / Y when several series share the rows
                                     // (beams stacked along the chunk axis); 0 = n_chunks
   float add_full = 0.0f;            // constant restored in chunks wholly inside the data
+  int full_chunks = -1;             // inverse: chunks 0 .. full_chunks-1 lie wholly inside the data
+                                    // (-1: decide from n_samp and the transform length)
+  float inv_n = 0.0f;               // inverse: scale applied after the half-length transform
+                                    // (0: 1 / (L/2), i.e. 1/L overall; shortened inverses use 2/L_full)
   unsigned int* l1max = nullptr;    // forward: per-chunk max L1 norm (float bits), or null
   int log_n = 0;                    // log2 of the complex points per series (L / 2)
 };
@@ -215,9 +219,21 @@ hipError_t launch_phasor_valu_grouped(int nk, const Group<PhasorArgs>& g, hipStr
 constexpr int kMfmaF32Variants = 5;
 
 // Byte offsets of the workspace regions (256-byte aligned).
+// A run of consecutive DMs that share one output down-sampling factor d.  Its phase table is
+// its own [n_chan][n] block of the plan's table, its output rows follow each other from
+// out_off, and its inverse transforms have length L/d with their own twiddle table.
+struct Segment {
+  int j0 = 0, n = 0;                  // DMs j0 .. j0 + n - 1
+  int factor = 1;                     // d
+  int64_t n_out = 0;                  // samples per output row, ceil(n_samp / d)
+  int64_t out_off = 0;                // output sample where row j0 starts
+  size_t tab = 0;                     // first phase-table entry of the segment
+  size_t tw = 0;                      // workspace byte offset of its twiddles exp(-2 pi i j d / L), j < L/d
+};
+
 struct WorkspaceLayout {
-  size_t tw = 0, tw_bytes = 0;        // float2 twiddles, L entries
-  size_t ptab = 0, ptab_bytes = 0;    // uint4 [n_chan][n_dm] phase increments and step phasors
+  size_t tw = 0, tw_bytes = 0;        // float2 twiddles: L entries, then L/d for every other factor d
+  size_t ptab = 0, ptab_bytes = 0;    // uint4 phase increments and step phasors, [n_chan][n] per segment
   size_t scale = 0, scale_bytes = 0;  // float [n_chunks]
   size_t xt = 0, xt_bytes = 0;        // transposed uint8 input
   size_t X = 0, X_bytes = 0;          // float2 [n_chan][n_chunks][pitch]
@@ -247,6 +263,11 @@ struct fdd_plan_s {
   int tdd_span = 0;                     // largest delay spread over 8 consecutive DMs (time-domain kernel)
   int tdd_span64 = 0;                   // ... over tdd_tile64() consecutive DMs
   double fac_dm0 = 0.0, fac_step = 0.0;
+  // output down-sampling: the factor of every DM and the runs of equal factors (one segment
+  // of factor 1 without down-sampling)
+  std::vector<int32_t> ds;
+  std::vector<fdd::Segment> segs;
+  int64_t out_total = 0;
   // stage timing: a ring of `prof_depth` calls x 5 events
   int prof_depth = 0;
   int64_t prof_calls = 0;               // calls recorded since the last read
@@ -259,6 +280,8 @@ namespace fdd {
 // increments and step phasors of every (channel, DM), channel-major.
 void twiddle_table(int64_t L, std::vector<float2>* out);
 void phase_table(const fdd_plan_s* p, std::vector<uint4>* out);
+// phase table of the DMs j0 .. j0 + n - 1 only, [n_chan][n]
+void phase_table_rows(const fdd_plan_s* p, int j0, int n, std::vector<uint4>* out);
 // DM factorisation: whether the DM list is DM_0 + j dDM (dDM > 0), and the coarse [n_chan][coarse]
 // plus fine [n_chan][fine] phase tables of trial a * fine + b.
 bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step);

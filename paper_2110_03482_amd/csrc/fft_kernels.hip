@@ -165,7 +165,7 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   const int64_t row = ((int64_t)dm * row_chunks + k) * pitch;
   const float* yr = Yr + row;
   const float* yi = Yi + row;
-  const float scale = 1.0f / (float)N;
+  const float scale = a.inv_n > 0.0f ? a.inv_n : 1.0f / (float)N;
   float2 v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
@@ -182,7 +182,8 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   }
   F::run(v, lds);
   const int64_t s0 = (int64_t)k * stride;
-  const float add = (s0 + L <= n_samp) ? add_full : 0.0f;
+  const bool full = a.full_chunks >= 0 ? k < a.full_chunks : s0 + L <= n_samp;
+  const float add = full ? add_full : 0.0f;
   float* dst = out + (int64_t)dm * n_samp + s0;
   const int64_t lim = (keep < n_samp - s0) ? keep : n_samp - s0;
 #pragma unroll

@@ -89,6 +89,10 @@ static void phase_rows(const fdd_plan_s* p, const double* dms, size_t nd, std::v
 
 void phase_table(const fdd_plan_s* p, std::vector<uint4>* out) { phase_rows(p, p->dms.data(), p->dms.size(), out); }
 
+void phase_table_rows(const fdd_plan_s* p, int j0, int n, std::vector<uint4>* out) {
+  phase_rows(p, p->dms.data() + j0, (size_t)n, out);
+}
+
 // DM-factorised tables: coarse trials DM_0 + a B dDM (channel-major [n_chan][A]) followed by
 // fine offsets b dDM ([n_chan][B]); the delays of trial a B + b add up to DM_j kappa_c.
 void factor_tables(const fdd_plan_s* p, int fine, int coarse, double dm0, double step, std::vector<uint4>* out) {
@@ -137,11 +141,24 @@ static fdd_status upload_tables(fdd_plan_s* p) {
   const WorkspaceLayout& w = p->ws;
   std::vector<float2> tw;
   twiddle_table(p->L, &tw);
-  hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), w.tw_bytes, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddles)");
+  for (const Segment& sg : p->segs) {
+    if (sg.factor == 1) continue;
+    twiddle_table(p->L / sg.factor, &tw);   // several segments may share a factor: same bytes
+    e = hipMemcpy(p->d_ws + sg.tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(short twiddles)");
+  }
   std::vector<uint4> tab;
-  if (p->fac_fine > 0) factor_tables(p, p->fac_fine, p->fac_coarse, p->fac_dm0, p->fac_step, &tab);
-  else phase_table(p, &tab);
+  if (p->fac_fine > 0) {
+    factor_tables(p, p->fac_fine, p->fac_coarse, p->fac_dm0, p->fac_step, &tab);
+  } else {
+    std::vector<uint4> part;
+    for (const Segment& sg : p->segs) {
+      phase_table_rows(p, sg.j0, sg.n, &part);
+      tab.insert(tab.end(), part.begin(), part.end());
+    }
+  }
   e = hipMemcpy(p->d_ws + w.ptab, tab.data(), tab.size() * sizeof(uint4), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase table)");
   std::vector<int> dt;
@@ -159,8 +176,31 @@ static fdd_status layout(fdd_plan_s* p) {
     *at = off;
     off = align_up(off + bytes);
   };
-  w.tw_bytes = (size_t)p->L * sizeof(float2);
+  // twiddles: L entries, then one table of L/d entries per distinct factor d > 1
+  {
+    std::vector<std::pair<int, size_t>> at;   // factor -> byte offset within the region
+    size_t tb = align_up((size_t)p->L * sizeof(float2));
+    for (Segment& sg : p->segs) {
+      if (sg.factor == 1) continue;
+      size_t o = 0;
+      bool seen = false;
+      for (const auto& pr : at)
+        if (pr.first == sg.factor) {
+          o = pr.second;
+          seen = true;
+        }
+      if (!seen) {
+        o = tb;
+        at.push_back({sg.factor, o});
+        tb = align_up(tb + (size_t)(p->L / sg.factor) * sizeof(float2));
+      }
+      sg.tw = o;                                // made absolute below
+    }
+    w.tw_bytes = tb;
+  }
   put(&w.tw, w.tw_bytes);
+  for (Segment& sg : p->segs)
+    if (sg.factor != 1) sg.tw += w.tw;
   const size_t rows_tab = std::max((size_t)d.n_dm, (size_t)p->fac_coarse + (size_t)p->fac_fine);
   if (!mul_ok((size_t)d.n_chan * rows_tab, sizeof(uint4), &w.ptab_bytes))
     return fail(FDD_E_NOMEM, "phase table size overflows");
@@ -232,6 +272,37 @@ fdd_status fdd_dispersion_delays(int32_t n_chan, const double* freqs, double ref
   return FDD_OK;
 }
 
+fdd_status fdd_smearing_factors(int32_t n_chan, const double* freqs, double tsamp, int32_t n_dm, const double* dm,
+                                int32_t max_factor, int32_t* out) {
+  if (n_chan < 1 || n_dm < 0 || freqs == nullptr || (n_dm > 0 && (dm == nullptr || out == nullptr)))
+    return fail(FDD_E_INVALID, "null or empty arguments");
+  if (!(tsamp > 0.0) || !std::isfinite(tsamp)) return fail(FDD_E_INVALID, "tsamp must be finite and > 0");
+  if (max_factor < 1 || (max_factor & (max_factor - 1)) != 0) return fail(FDD_E_INVALID, "max_factor must be a power of two >= 1");
+  std::vector<double> f(freqs, freqs + n_chan);
+  for (double v : f)
+    if (!(v > 0.0) || !std::isfinite(v)) return fail(FDD_E_INVALID, "channel frequencies must be finite and > 0");
+  std::sort(f.begin(), f.end());
+  double w = 0.0;
+  for (size_t c = 1; c < f.size(); ++c) {
+    const double g = f[c] - f[c - 1];
+    if (g > 0.0 && (w == 0.0 || g < w)) w = g;
+  }
+  // Eq. 1 across the lowest channel, per unit DM, in samples
+  double per_dm = 0.0;
+  if (w > 0.0 && f[0] - 0.5 * w > 0.0) {
+    const double lo = f[0] - 0.5 * w, hi = f[0] + 0.5 * w;
+    per_dm = FDD_K_DM * (1.0 / (lo * lo) - 1.0 / (hi * hi)) / tsamp;
+  }
+  for (int32_t m = 0; m < n_dm; ++m) {
+    if (!(dm[m] >= 0.0) || !std::isfinite(dm[m])) return fail(FDD_E_INVALID, "DMs must be finite and >= 0");
+    const double sm = dm[m] * per_dm;
+    int32_t d = 1;
+    while (d < max_factor && 2.0 * d <= sm) d *= 2;
+    out[m] = d;
+  }
+  return FDD_OK;
+}
+
 fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
   if (desc == nullptr || out == nullptr) return fail(FDD_E_INVALID, "null descriptor or output");
   *out = nullptr;
@@ -255,14 +326,30 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     const double v = d.dm[m];
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(FDD_E_INVALID, "DMs must be finite and >= 0");
   }
+  int32_t max_ds = 1;
+  if (d.downsample != nullptr) {
+    for (int32_t m = 0; m < d.n_dm; ++m) {
+      const int32_t f = d.downsample[m];
+      if (f < 1 || (f & (f - 1)) != 0 || (int64_t)f * 64 > L)
+        return fail(FDD_E_INVALID, "down-sampling factors must be powers of two from 1 to chunk_len/64");
+      max_ds = std::max(max_ds, f);
+    }
+    if (max_ds > 1 && (d.flags & FDD_PLAN_POWER_ONLY))
+      return fail(FDD_E_INVALID, "down-sampling shortens the inverse transform; a power-only plan has none");
+    if (max_ds > 1 && L > (int64_t(1) << (kMaxBlockLogN + 1)))
+      return fail(FDD_E_UNSUPPORTED, "down-sampled output needs chunk_len <= 2^16");
+  }
 
   fdd_plan_s* p = new (std::nothrow) fdd_plan_s();
   if (p == nullptr) return fail(FDD_E_NOMEM, "host allocation failed");
   p->desc = d;
   p->freqs.assign(d.chan_freq_mhz, d.chan_freq_mhz + d.n_chan);
   p->dms.assign(d.dm, d.dm + d.n_dm);
+  p->ds.assign((size_t)d.n_dm, 1);
+  if (d.downsample != nullptr) p->ds.assign(d.downsample, d.downsample + d.n_dm);
   p->desc.chan_freq_mhz = p->freqs.data();
   p->desc.dm = p->dms.data();
+  p->desc.downsample = p->ds.data();
   p->kappa.resize((size_t)d.n_chan);
   double kmax = 0.0, dmax = 0.0;
   for (int32_t c = 0; c < d.n_chan; ++c) {
@@ -297,8 +384,38 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
       delete p;
       return fail(FDD_E_OVERLAP, "overlap must be shorter than chunk_len; use a longer chunk");
     }
+    // every down-sampled chunk keeps S/d whole output samples
+    if ((L - p->D) % max_ds != 0) {
+      if (d.overlap > 0) {
+        delete p;
+        return fail(FDD_E_INVALID, "chunk_len - overlap must be a multiple of the largest down-sampling factor " +
+                                       std::to_string(max_ds));
+      }
+      p->D = L - (L - p->D) / max_ds * max_ds;
+      if (p->D >= L) {
+        delete p;
+        return fail(FDD_E_OVERLAP, "no kept stride is a multiple of the largest down-sampling factor; use a longer chunk");
+      }
+    }
     p->S = L - p->D;
     p->n_chunks = (d.n_samp + p->S - 1) / p->S;
+  }
+  // runs of equal down-sampling factors, their output rows and phase-table blocks
+  for (int32_t m = 0; m < d.n_dm;) {
+    Segment sg;
+    sg.j0 = m;
+    sg.factor = p->ds[(size_t)m];
+    while (m < d.n_dm && p->ds[(size_t)m] == sg.factor) ++m;
+    sg.n = m - sg.j0;
+    sg.n_out = (d.n_samp + sg.factor - 1) / sg.factor;
+    sg.out_off = p->out_total;
+    sg.tab = (size_t)d.n_chan * (size_t)sg.j0;
+    p->out_total += (int64_t)sg.n * sg.n_out;
+    p->segs.push_back(sg);
+  }
+  if (p->segs.size() > 256) {
+    delete p;
+    return fail(FDD_E_UNSUPPORTED, "more than 256 runs of equal down-sampling factors; sort the DMs by factor");
   }
   p->n_valid = d.n_samp - need > 0 ? d.n_samp - need : 0;
   if (p->n_chunks > 65535 || d.n_dm > 65535 * 4 || d.n_chan > 65535) {
@@ -327,7 +444,7 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     const bool all = fe != nullptr && std::strcmp(fe, "all") == 0;
     const int fine = phasor_fac_fine((int)p->n_chunks);
     double dm0 = 0.0, step = 0.0;
-    if (!off && d.delay_mode == FDD_DELAY_EXACT && fine > 0 && (all || p->n_chunks <= 2) &&
+    if (!off && d.delay_mode == FDD_DELAY_EXACT && fine > 0 && (all || p->n_chunks <= 2) && max_ds == 1 &&
         uniform_grid(p->dms, &dm0, &step)) {
       p->fac_fine = fine;
       p->fac_coarse = (d.n_dm + fine - 1) / fine;
@@ -389,6 +506,16 @@ fdd_status fdd_plan_info(fdd_plan_t p, fdd_plan_geometry* g) {
   g->max_delay = p->max_tau;
   g->n_valid = p->n_valid;
   g->workspace_bytes = p->ws.total;
+  g->out_samples = p->out_total;
+  g->n_segments = (int32_t)p->segs.size();
+  return FDD_OK;
+}
+
+fdd_status fdd_plan_output_offsets(fdd_plan_t p, int64_t* off) {
+  if (p == nullptr || off == nullptr) return fail(FDD_E_INVALID, "null plan or output");
+  for (const Segment& sg : p->segs)
+    for (int i = 0; i < sg.n; ++i) off[sg.j0 + i] = sg.out_off + (int64_t)i * sg.n_out;
+  off[p->desc.n_dm] = p->out_total;
   return FDD_OK;
 }
 

@@ -171,3 +171,94 @@ def test_batch_rejects_without_device_calls():
     assert lib.fdd_batch_info(None, None, None, None) == 1
     assert lib.fdd_batch_destroy(None) == 0
     p.close()
+
+
+# ----------------------------------------------------------------------------- down-sampled output (Sec. 2.2)
+
+def test_downsampled_geometry_and_offsets():
+    w = W.paper_shaped_u8()
+    ds = np.ones(w.n_dm, dtype=np.int32)
+    ds[100:300] = 4
+    ds[300:] = 16
+    ds[50] = 2                                           # runs need not be monotone
+    p = _dry(w, downsample=ds)
+    g = p.geometry
+    assert (g.chunk_len - g.overlap) % 16 == 0 and g.stride % 16 == 0
+    n_out = -(-w.n_samp // ds.astype(np.int64))
+    assert g.out_samples == int(n_out.sum()) and p.downsampled
+    assert g.n_segments == 5                             # 1 | 2 | 1 | 4 | 16
+    off = p.output_offsets()
+    np.testing.assert_array_equal(off, np.concatenate([[0], np.cumsum(n_out)]))
+    assert p.kernel == "mfma_f32"
+    p.close()
+    flat = _dry(w, downsample=np.ones(w.n_dm, dtype=np.int32))
+    assert not flat.downsampled and flat.geometry.n_segments == 1
+    assert flat.geometry.out_samples == w.n_dm * w.n_samp
+    flat.close()
+    # ceil(max tau) = 14496 already leaves S = 51040 = 16 x 3190: the overlap stays
+    assert _dry(w).geometry.overlap == 14496 and g.overlap == 14496
+
+
+def test_downsampled_overlap_rounding_and_rejections():
+    w = W.small_fp32()
+    n = w.n_dm
+    auto = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, 20000, 4096, input="f32", dry_run=True,
+                    downsample=np.full(n, 8, dtype=np.int32))
+    base = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, 20000, 4096, input="f32", dry_run=True)
+    D0 = base.geometry.overlap
+    assert auto.geometry.overlap == 4096 - (4096 - D0) // 8 * 8 and auto.geometry.stride % 8 == 0
+    assert auto.kernel != "fac_f32"                      # the factorised tables serve one segment of factor 1
+    cases = [
+        (dict(downsample=np.full(n, 3, dtype=np.int32)), 1),             # not a power of two
+        (dict(downsample=np.zeros(n, dtype=np.int32)), 1),               # below 1
+        (dict(downsample=np.full(n, 4096 // 32, dtype=np.int32)), 1),    # L/d below 64
+        (dict(downsample=np.full(n, 2, dtype=np.int32), power_only=True, single_chunk=True), 1),
+        (dict(downsample=np.full(n, 8, dtype=np.int32), overlap=D0 + 1 if (4096 - D0 - 1) % 8 else D0 + 2), 1),
+    ]
+    for kw, status in cases:
+        args = dict(input="f32", dry_run=True)
+        args.update(kw)
+        ns = 4096 if args.get("single_chunk") else 20000
+        with pytest.raises(fdd.FddError) as e:
+            fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, ns, 4096, **args)
+        assert e.value.status == status, kw
+    with pytest.raises(fdd.FddError) as e:              # shortened inverses use the one-workgroup transforms
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, 1 << 17, 1 << 17, single_chunk=True, input="f32",
+                 dry_run=True, downsample=np.full(n, 2, dtype=np.int32))
+    assert e.value.status == 3
+    many = np.tile(np.array([1, 2], dtype=np.int32), 200)
+    dms = np.linspace(0.0, 10.0, many.size)
+    with pytest.raises(fdd.FddError) as e:
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, dms, 20000, 4096, input="f32", dry_run=True, downsample=many)
+    assert e.value.status == 3 and "runs" in str(e.value)
+    with pytest.raises(ValueError):
+        fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, 20000, 4096, input="f32", dry_run=True,
+                 downsample=np.ones(n + 1, dtype=np.int32))
+
+
+def test_batch_rejects_downsampled_plans():
+    w = W.small_fp32()
+    p = _dry(w, downsample=np.full(w.n_dm, 2, dtype=np.int32))
+    # planned without a device, so the batch stops at the dry-run check first; the factor
+    # check sits behind it and is exercised on the GPU
+    with pytest.raises(fdd.FddError):
+        fdd.fdd_batch_create([p.handle], fdd.BatchDesc())
+    p.close()
+
+
+def test_smearing_factors():
+    # two channels 1 MHz apart at 400.5 / 401.5 MHz: the lowest channel spans 400 .. 401 MHz
+    freqs = np.array([401.5, 400.5])
+    tsamp = 1e-4
+    per_dm = 4.148808e3 * (1.0 / 400.0 ** 2 - 1.0 / 401.0 ** 2) / tsamp     # samples per unit DM
+    dms = np.array([0.0, 0.99 / per_dm, 1.0 / per_dm * 1.000001, 3.99 / per_dm, 4.0 / per_dm * 1.000001,
+                    1000.0 / per_dm])
+    got = fdd.fdd_smearing_factors(freqs, tsamp, dms, 64)
+    np.testing.assert_array_equal(got, [1, 1, 1, 2, 4, 64])
+    np.testing.assert_array_equal(fdd.fdd_smearing_factors(freqs, tsamp, dms, 8), [1, 1, 1, 2, 4, 8])
+    np.testing.assert_array_equal(fdd.fdd_smearing_factors([1400.0], tsamp, dms, 64), np.ones(6))
+    w = W.paper_shaped_u8()
+    f = fdd.fdd_smearing_factors(w.freqs, w.tsamp_s, w.dms, 16)
+    assert f[0] == 1 and f[-1] == 16 and np.all(np.diff(f) >= 0)          # ascending DMs: runs ascend
+    with pytest.raises(fdd.FddError):
+        fdd.fdd_smearing_factors(freqs, tsamp, dms, 3)

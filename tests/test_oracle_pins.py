@@ -153,6 +153,94 @@ def test_tone_closed_form_chunked():
     np.testing.assert_allclose(y[:, inside], want[:, inside], atol=1e-9)
 
 
+# ----------------------------------------------------------------------------- down-sampled inverse, Sec. 2.2
+
+@pytest.mark.parametrize("d,k0", [(2, 1), (2, 255), (4, 100), (8, 63), (16, 3)])
+def test_downsampled_tone_closed_form_single_chunk(d, k0):
+    """A tone below the shortened band (k0 < L/(2d)) comes out advanced by tau and sampled
+    every d-th sample, with its full amplitude (the 1/L scaling)."""
+    L = 2048
+    assert k0 < L // (2 * d)
+    freqs, dms, theta, x = _tone_problem(L, L, k0, seed=10 + k0)
+    tau = O.delays(dms, freqs, 1500.0, 64e-6)
+    z = O.oracle_fdd_rows(x, "f64", tau, L, L, 1, True, "exact", factors=[d] * len(dms))
+    m = np.arange(L // d)
+    want = np.cos(2 * np.pi * k0 * (d * m[None, None, :] + tau[:, :, None]) / L
+                  + theta[None, :, None]).sum(axis=1)
+    for i in range(len(dms)):
+        assert z[i].shape == (L // d,)
+        np.testing.assert_allclose(z[i], want[i], atol=1e-9)
+
+
+@pytest.mark.parametrize("d", [2, 4, 8])
+def test_downsampled_tone_closed_form_chunked(d):
+    """Overlap-save with a kept stride that is a multiple of d: chunks inside the data give
+    the closed form at every d-th sample; the rows hold ceil(n_samp / d) samples."""
+    L, k0 = 1024, 21
+    n_samp = 5001
+    freqs, dms, theta, x = _tone_problem(L, n_samp, k0, seed=4)
+    tau = O.delays(dms, freqs, 1500.0, 64e-6)
+    S, n_chunks, D = O.chunk_geometry(n_samp, L, 0, False, float(tau.max()), d)
+    assert S % d == 0 and D >= np.ceil(tau.max())
+    z = O.oracle_fdd_rows(x, "f64", tau, L, S, n_chunks, False, "exact", factors=[d] * len(dms))
+    n_out = -(-n_samp // d)
+    m = np.arange(n_out)
+    want = np.cos(2 * np.pi * k0 * (d * m[None, None, :] + tau[:, :, None]) / L
+                  + theta[None, :, None]).sum(axis=1)
+    inside = np.zeros(n_out, dtype=bool)
+    for k in range(n_chunks):
+        if k * S + L <= n_samp:
+            inside[k * S // d: (k + 1) * S // d] = True
+    assert inside.sum() >= 2 * S // d
+    for i in range(len(dms)):
+        assert z[i].shape == (n_out,)
+        np.testing.assert_allclose(z[i][inside], want[i][inside], atol=1e-9)
+
+
+def test_downsampled_equals_decimated_full_resolution_when_band_limited():
+    """Random spectra confined to bins 1 .. L/(2d) - 1: the shortened inverse is exactly every
+    d-th sample of the full-resolution series, for mixed factors in one DM list."""
+    L, d_list = 1024, [1, 2, 2, 8, 4, 1]
+    rng = np.random.default_rng(5)
+    n_chan = 6
+    spec = np.zeros((n_chan, L // 2 + 1), dtype=np.complex128)
+    top = L // (2 * max(d_list))
+    spec[:, 1:top] = rng.standard_normal((n_chan, top - 1)) + 1j * rng.standard_normal((n_chan, top - 1))
+    x = np.fft.irfft(spec, n=L, axis=-1)
+    freqs = np.sort(rng.uniform(1200.0, 1500.0, n_chan))
+    dms = rng.uniform(0.0, 20.0, len(d_list))
+    tau = O.delays(dms, freqs, 1500.0, 64e-6)
+    full = O.oracle_fdd_rows(x, "f64", tau, L, L, 1, True, "exact")
+    z = O.oracle_fdd_rows(x, "f64", tau, L, L, 1, True, "exact", factors=d_list)
+    for i, d in enumerate(d_list):
+        np.testing.assert_allclose(z[i], full[i][::d], atol=1e-12 * np.abs(full[i]).max())
+
+
+def test_downsampled_cutoff_bin_half_weight_and_above_removed():
+    """Reading of the cutoff: a tone at bin M/2 = L/(2d) keeps half its amplitude; one bin
+    above it is removed entirely."""
+    L, d = 512, 4
+    M = L // d
+    t = np.arange(L)
+    tau = np.zeros((1, 1))
+    at = np.cos(2 * np.pi * (M // 2) * t / L)[None, :]
+    above = np.cos(2 * np.pi * (M // 2 + 1) * t / L)[None, :]
+    z_at = O.oracle_fdd_rows(at, "f64", tau, L, L, 1, True, "exact", factors=[d])[0]
+    z_above = O.oracle_fdd_rows(above, "f64", tau, L, L, 1, True, "exact", factors=[d])[0]
+    m = np.arange(M)
+    np.testing.assert_allclose(z_at, 0.5 * np.where(m % 2 == 0, 1.0, -1.0), atol=1e-12)
+    np.testing.assert_allclose(z_above, 0.0, atol=1e-12)
+
+
+def test_downsampled_stride_rule():
+    """An automatic overlap grows until S is a multiple of the largest factor; an explicit
+    overlap that does not give that is rejected."""
+    S, n, D = O.chunk_geometry(10000, 1024, 0, False, 100.3, 16)
+    assert D == 112 and S == 912 and n == -(-10000 // 912)
+    with pytest.raises(ValueError):
+        O.chunk_geometry(10000, 1024, 101, False, 100.3, 16)
+
+
 @pytest.mark.parametrize("t0,tau", [(100, 3.25), (0, 0.5), (511, 17.75), (37, 200.1)])
 def test_dirichlet_closed_form(t0, tau):
     """A delta advanced by a fractional delay: closed-form periodic sinc, incl. the Nyquist term."""
