@@ -361,14 +361,15 @@ def main() -> int:
     xd = torch.from_numpy(x).to(dev)
     samples = w.n_dm * w.n_samp
 
-    def run_form(precision: str) -> dict:
+    def run_form(precision: str, factors=None) -> dict:
         plan = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, overlap=w.overlap,
                         single_chunk=w.single_chunk, input=w.input_kind, precision=precision, mode=args.mode,
-                        device=dev)
+                        device=dev, downsample=factors)
         g = plan.geometry
-        out = torch.empty((w.n_dm, w.n_samp), dtype=torch.float32, device=dev)
+        shape = (int(g.out_samples),) if plan.downsampled else (w.n_dm, w.n_samp)
+        out = torch.empty(shape, dtype=torch.float32, device=dev)
         log(f"{precision}: L={g.chunk_len} S={g.stride} D={g.overlap} chunks={g.n_chunks} kernel={plan.kernel} "
-            f"workspace={g.workspace_bytes / 2**30:.2f} GiB")
+            f"segments={g.n_segments} workspace={g.workspace_bytes / 2**30:.2f} GiB")
         for i in range(args.warmup):
             plan.execute(xd, out)
             torch.cuda.synchronize()
@@ -386,7 +387,7 @@ def main() -> int:
         res = {"precision": precision, "kernel": plan.kernel, "ms_per_step": ms, "value": samples / (ms * 1e-3),
                "stages_ms": {"transpose": stage_ms[0], "forward_fft": stage_ms[1], "phasor_sum": stage_ms[2],
                              "inverse_fft": stage_ms[3]},
-               "geometry": g}
+               "geometry": g, "factors": factors}
         plan.close()
         del out
         torch.cuda.empty_cache()
@@ -409,15 +410,27 @@ def main() -> int:
 
     forms = [run_form(p) for p in (["fp32", "fp16_split", "bf16_split"] if args.precision == "all" else [args.precision])]
     tdd_form = run_tdd() if args.precision == "all" else None
+    # down-sampled output (Sec. 2.2): factors from the smearing across the lowest channel
+    ds_factors = fdd.fdd_smearing_factors(w.freqs, w.tsamp_s, w.dms, 16)
+    ds_forms = [run_form(p, ds_factors) for p in (["fp32", "fp16_split"] if args.precision == "all"
+                                                    else [args.precision])]
     main_form = forms[0]
     g = main_form["geometry"]
     flops = 8.0 * w.n_dm * w.n_chan * g.n_bins * g.n_chunks      # complex MACs of Eq. 7, 8 flops each
 
+    def form_flops(form: dict) -> float:
+        fg = form["geometry"]
+        if form["factors"] is None:
+            return flops
+        bins = (int(fg.chunk_len) // (2 * form["factors"].astype(np.int64)) + 1).sum()
+        return 8.0 * w.n_chan * float(bins) * fg.n_chunks
+
     def roofline(form: dict) -> dict:
+        flops = form_flops(form)
         achieved = flops / (form["stages_ms"]["phasor_sum"] * 1e-3) / 1e12
         peak = {"fp32": PEAK["fp32_mfma_TFLOPs"], "fp16_split": PEAK["fp16_mfma_TFLOPs"],
                 "bf16_split": PEAK["bf16_mfma_TFLOPs"]}[form["precision"]]
-        wl = w.name + f"_{args.mode}_{form['precision']}"
+        wl = w.name + f"_{args.mode}_{form['precision']}" + ("" if form["factors"] is None else "_downsampled")
         return {"kernel": f"phasor_sum_{form['kernel']}", "bound": "alu" if form["kernel"] == "valu" else "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(form["kernel"], wl), "algorithmic_flops_per_launch": flops}
@@ -452,6 +465,14 @@ def main() -> int:
     }
     if tdd_form is not None:
         result["forms"]["tdd_u8"] = tdd_form
+    counts = {int(d): int(n) for d, n in zip(*np.unique(ds_factors, return_counts=True))}
+    for f in ds_forms:
+        result["forms"][f["precision"] + "_downsampled"] = {
+            "value": f["value"], "ms_per_step": f["ms_per_step"], "stages_ms": f["stages_ms"],
+            "roofline": roofline(f), "segments": int(f["geometry"].n_segments), "factor_counts": counts,
+            "output_samples": int(f["geometry"].out_samples),
+            "note": "DMs whose smearing spans d >= 2 samples are inverted at L/d (Sec. 2.2); value counts input "
+                    "samples per DM, as for the full-resolution forms"}
     del xd
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
