@@ -82,6 +82,7 @@ typedef enum {
 #define FDD_PLAN_DRY_RUN 1u             /* validate and size only; no device calls at all */
 #define FDD_PLAN_EXTERNAL_WORKSPACE 2u  /* caller attaches the workspace with fdd_set_workspace */
 #define FDD_PLAN_POWER_ONLY 4u          /* the plan will only compute power spectra: no inverse buffers */
+#define FDD_PLAN_SCALED_DM 8u           /* also size the workspace for fdd_power_spectrum_scaled */
 
 typedef struct {
   int32_t n_chan;               /* channels, >= 1 */
@@ -119,6 +120,7 @@ typedef struct {
   int64_t out_samples;      /* float32 samples fdd_execute writes: sum over DMs of ceil(n_samp / d_dm)
                                (n_dm * n_samp without down-sampling) */
   int32_t n_segments;       /* runs of consecutive DMs with one down-sampling factor (1 without) */
+  int64_t scaled_min_bin;   /* FDD_PLAN_SCALED_DM: first bin of the approximate region (0 otherwise) */
 } fdd_plan_geometry;
 
 typedef struct fdd_plan_s* fdd_plan_t;
@@ -153,6 +155,21 @@ fdd_status fdd_plan_output_offsets(fdd_plan_t plan, int64_t* offsets);
  * |Y[dm, f]|^2 for f = 0 .. L/2-1 (down-sampling factors do not apply).  Single-chunk plans
  * only (FDD_E_UNSUPPORTED otherwise). */
 fdd_status fdd_power_spectrum(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
+
+/* Power spectra with spin-frequency-scaled DMs (Sec. 2.3, Eq. 8): an approximation, for plans
+ * made with FDD_PLAN_SCALED_DM (single chunk, exact delays, a uniform DM list
+ * DM_j = DM_0 + j dDM, n_dm >= 2).  Bins f >= f_min (geometry scaled_min_bin) are cut into
+ * blocks of 64 with reference bin r = (first bin) + 32.  Within a block, row s of the scaled
+ * grid (DM'_s = DM_0 + s dDM, s = -32 .. n_dm + 31) uses at bin f the DM DM'_s r / f, whose
+ * phasor exp(+2 pi i r DM'_s kappa_c / L) does not depend on f, so the block's phasor sum is
+ * one matrix product Q[s, f] = |sum_c W_r[s, c] X[c, f]|^2.  The power at trial DM_j and bin
+ * f is then resampled linearly in DM:
+ *     s* = (DM_j f / r - DM_0) / dDM,  P[j, f] = (1 - w) Q[floor(s*), f] + w Q[floor(s*) + 1, f],
+ * w = s* - floor(s*).  f_min is the smallest block start (at least 64) for which
+ * |s* - j| <= 31 everywhere; bins below it are computed exactly as fdd_power_spectrum does.
+ * Output float32 [n_dm][L/2].
+ * Errors: FDD_E_UNSUPPORTED for a plan without FDD_PLAN_SCALED_DM; as fdd_power_spectrum. */
+fdd_status fdd_power_spectrum_scaled(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
 /* Brute-force time-domain dedispersion (Eq. 2), the method FDD is compared with (Sec. 4.1):
  *     d_out[dm][t] = sum_c x[c][t + d[dm][c]],   d = floor(tau + 1/2)   (the plan's delays)

@@ -17,6 +17,9 @@ What is computed, in the paper's order and notation:
   channels (Eq. 7), one inverse FFT per DM (Eq. 6), discarding the cyclically contaminated
   end of every series (Sec. 2.2, wrap/discard rule).
 * Sec. 5: power spectra |I(f_s, DM)|^2 taken directly from the Fourier-domain result.
+* Sec. 2.3, Eq. 8: spin-frequency-scaled DMs.  Scaling a trial DM as DM_ref r / f_s makes the
+  phasor of bin f_s equal to that of the reference bin r at DM_ref, so one phasor matrix serves
+  a range of bins; the result is then resampled onto the trial DMs (an approximation).
 
 Readings where the paper is silent or inconsistent (all listed in the design notes):
 
@@ -68,6 +71,8 @@ __all__ = [
     "input_segment",
     "oracle_fdd_rows",
     "inverse_real_short",
+    "scaled_phasors",
+    "fdd_power_scaled",
 ]
 
 # Dispersion constant in MHz^2 pc^-1 cm^3 s (Eq. 1).
@@ -298,6 +303,66 @@ def fdd_power(x: np.ndarray, kind: str, dms, freqs_mhz, ref_freq_mhz: float, tsa
     """Power spectra |Y[dm, f]|^2, f < L/2, of the single-chunk FDD (Sec. 5)."""
     tau = delays(dms, freqs_mhz, ref_freq_mhz, tsamp_s)
     return oracle_fdd_rows(x, kind, tau, chunk_len, chunk_len, 1, True, mode, rows, power=True)
+
+
+# --------------------------------------------------------------------------- Sec. 2.3, Eq. 8: scaled DMs
+
+def scaled_phasors(kappa_c: np.ndarray, dm: np.ndarray, ref_bin: int, L: int) -> np.ndarray:
+    """Eq. 8: the phasor of reference bin r at DM, exp(+2 pi i frac(r DM kappa_c / L)), which by
+    the substitution DM_f = DM r / f is also the phasor of every bin f at DM r / f.
+    Returns [len(dm), n_chan]."""
+    tau = np.asarray(dm, dtype=np.float64)[:, None] * np.asarray(kappa_c, dtype=np.float64)[None, :]
+    v = tau * float(ref_bin) / L
+    return np.exp(2j * np.pi * (v - np.floor(v)))
+
+
+def fdd_power_scaled(x: np.ndarray, kind: str, dms, freqs_mhz, ref_freq_mhz: float, tsamp_s: float,
+                     chunk_len: int, f_min: int, block: int = 64, halo: int = 32,
+                     rows: Optional[Iterable[int]] = None, bins: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Power spectra of one chunk with spin-frequency-scaled DMs (Sec. 2.3, Eq. 8).
+
+    Bins below f_min are exact (as fdd_power).  From f_min on, bins form blocks of `block`
+    with reference bin r = block start + block/2; the scaled grid DM'_s = DM_0 + s dDM
+    (s = -halo .. n_dm + halo - 1) of a block is evaluated with the phasors of bin r, which
+    at bin f belong to the DM DM'_s r / f.  Trial DM_j at bin f therefore lies at the
+    fractional row s* = (DM_j f / r - DM_0) / dDM, and its power is interpolated linearly
+    between rows floor(s*) and floor(s*) + 1:
+        P[j, f] = (1 - w) |Ytilde[floor(s*), f]|^2 + w |Ytilde[floor(s*) + 1, f]|^2.
+    The DM list must be uniform (DM_0 + j dDM).  Returns float64 [len(rows), len(bins)]
+    (all trials and bins 0 .. L/2 - 1 by default).
+    """
+    L = int(chunk_len)
+    dms = np.asarray(dms, dtype=np.float64)
+    n_dm = dms.size
+    dm0 = float(dms[0])
+    step = (float(dms[-1]) - dm0) / (n_dm - 1)
+    kap = kappa(freqs_mhz, ref_freq_mhz, tsamp_s)
+    rows = list(range(n_dm)) if rows is None else list(rows)
+    bins = np.arange(L // 2) if bins is None else np.asarray(bins, dtype=np.int64)
+    X = forward_spectra(input_segment(x, kind, 0, L))             # [n_chan, L/2 + 1], Eq. 3
+    out = np.zeros((len(rows), bins.size), dtype=np.float64)
+    low = bins < f_min
+    if np.any(low):
+        fl = bins[low]
+        for i, j in enumerate(rows):
+            W = phasors(dms[j] * kap, L, "exact")[:, fl]             # Eq. 4 at the trial DM
+            Y = np.sum(W * X[:, fl], axis=0)
+            out[i, low] = Y.real ** 2 + Y.imag ** 2
+    tr = dms[rows]
+    for k in np.nonzero(~low)[0]:
+        f = int(bins[k])
+        r = f_min + (f - f_min) // block * block + block // 2
+        ss = (tr * f / r - dm0) / step                               # fractional scaled rows
+        s0 = np.floor(ss)
+        w = ss - s0
+        if np.any(s0 < -halo) or np.any(s0 + 1 >= n_dm + halo):
+            raise ValueError("trial outside the scaled grid's halo")
+        p = []
+        for s in (s0, s0 + 1):
+            Yt = scaled_phasors(kap, dm0 + s * step, r, L) @ X[:, f]
+            p.append(Yt.real ** 2 + Yt.imag ** 2)
+        out[:, k] = (1.0 - w) * p[0] + w * p[1]
+    return out
 
 
 # --------------------------------------------------------------------------- definitions used as pins

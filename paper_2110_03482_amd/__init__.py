@@ -18,9 +18,9 @@ import numpy as np
 __all__ = [
     "FDD_OK", "FDD_IN_U8_TIME_MAJOR", "FDD_IN_F32_CHAN_MAJOR", "FDD_FP32", "FDD_FP16_SPLIT",
     "FDD_BF16_SPLIT", "FDD_DELAY_EXACT", "FDD_DELAY_ROUND", "FDD_PLAN_DRY_RUN",
-    "FDD_PLAN_EXTERNAL_WORKSPACE", "FDD_PLAN_POWER_ONLY", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
+    "FDD_PLAN_EXTERNAL_WORKSPACE", "FDD_PLAN_POWER_ONLY", "FDD_PLAN_SCALED_DM", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
     "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
-    "fdd_power_spectrum", "fdd_tdd_execute", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
+    "fdd_power_spectrum", "fdd_power_spectrum_scaled", "fdd_tdd_execute", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
     "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_output_offsets", "fdd_smearing_factors",
     "fdd_plan_kernel", "fdd_status_string",
     "fdd_last_error", "fdd_version", "Plan", "FDD_BATCH_NO_GRAPH", "FDD_BATCH_NO_AUTOTUNE", "FDD_BATCH_SHARE_PHASORS", "BatchDesc",
@@ -31,7 +31,7 @@ FDD_OK = 0
 FDD_IN_U8_TIME_MAJOR, FDD_IN_F32_CHAN_MAJOR = 0, 1
 FDD_FP32, FDD_FP16_SPLIT, FDD_BF16_SPLIT = 0, 1, 2
 FDD_DELAY_EXACT, FDD_DELAY_ROUND = 0, 1
-FDD_PLAN_DRY_RUN, FDD_PLAN_EXTERNAL_WORKSPACE, FDD_PLAN_POWER_ONLY = 1, 2, 4
+FDD_PLAN_DRY_RUN, FDD_PLAN_EXTERNAL_WORKSPACE, FDD_PLAN_POWER_ONLY, FDD_PLAN_SCALED_DM = 1, 2, 4, 8
 FDD_BATCH_NO_GRAPH, FDD_BATCH_NO_AUTOTUNE, FDD_BATCH_SHARE_PHASORS = 1, 2, 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +78,7 @@ class PlanGeometry(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("out_samples", ctypes.c_int64),
         ("n_segments", ctypes.c_int32),
+        ("scaled_min_bin", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -102,6 +103,7 @@ _SIGNATURES = {
     "fdd_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_power_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_tdd_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdd_power_spectrum_scaled": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "fdd_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "fdd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
@@ -195,6 +197,11 @@ def fdd_execute(plan, d_in: int, d_out: int, stream: int = 0) -> None:
 def fdd_power_spectrum(plan, d_in: int, d_out: int, stream: int = 0) -> None:
     _check(library().fdd_power_spectrum(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
                                         ctypes.c_void_p(stream)), "fdd_power_spectrum")
+
+
+def fdd_power_spectrum_scaled(plan, d_in: int, d_out: int, stream: int = 0) -> None:
+    _check(library().fdd_power_spectrum_scaled(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out),
+                                               ctypes.c_void_p(stream)), "fdd_power_spectrum_scaled")
 
 
 def fdd_tdd_execute(plan, d_in: int, d_out: int, stream: int = 0) -> None:
@@ -303,7 +310,7 @@ class Plan:
     def __init__(self, freqs_mhz, ref_freq_mhz: float, tsamp_s: float, dms, n_samp: int, chunk_len: int,
                  overlap: int = 0, single_chunk: bool = False, input: str = "f32", precision: str = "fp32",
                  mode: str = "exact", device=None, dry_run: bool = False, power_only: bool = False,
-                 workspace: bool = True, downsample=None):
+                 workspace: bool = True, downsample=None, scaled_dm: bool = False):
         self._freqs = np.ascontiguousarray(freqs_mhz, dtype=np.float64)
         self._dms = np.ascontiguousarray(dms, dtype=np.float64)
         self._ds = None if downsample is None else np.ascontiguousarray(downsample, dtype=np.int32)
@@ -326,7 +333,8 @@ class Plan:
         d.input = _INPUTS[input]
         d.precision = _PRECISIONS[precision]
         d.delay_mode = _MODES[mode]
-        d.flags = (FDD_PLAN_DRY_RUN if dry_run else FDD_PLAN_EXTERNAL_WORKSPACE) | (FDD_PLAN_POWER_ONLY if power_only else 0)
+        d.flags = ((FDD_PLAN_DRY_RUN if dry_run else FDD_PLAN_EXTERNAL_WORKSPACE) | (FDD_PLAN_POWER_ONLY if power_only else 0)
+                   | (FDD_PLAN_SCALED_DM if scaled_dm else 0))
         if self._ds is not None:
             if self._ds.size != self.n_dm:
                 raise ValueError("downsample needs one factor per DM")
@@ -414,6 +422,19 @@ class Plan:
         elif out.dtype != torch.float32 or tuple(out.shape) != (self.n_dm, nb) or not out.is_contiguous():
             raise ValueError("out must be a contiguous float32 tensor [n_dm][L/2]")
         fdd_power_spectrum(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
+        return out
+
+    def power_spectrum_scaled(self, x, out=None, stream=None):
+        """Power spectra float32 [n_dm][L/2] with spin-frequency-scaled DMs (approximate above
+        geometry.scaled_min_bin; plans made with scaled_dm=True)."""
+        import torch
+        self._check_input(x)
+        nb = int(self.geometry.chunk_len) // 2
+        if out is None:
+            out = torch.empty((self.n_dm, nb), dtype=torch.float32, device=self.device)
+        elif out.dtype != torch.float32 or tuple(out.shape) != (self.n_dm, nb) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor [n_dm][L/2]")
+        fdd_power_spectrum_scaled(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
         return out
 
     def profile(self, depth: int = 1) -> None:

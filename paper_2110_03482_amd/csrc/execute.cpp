@@ -215,4 +215,58 @@ fdd_status fdd_power_spectrum(fdd_plan_t p, const void* in, float* out, void* st
   return FDD_OK;
 }
 
+fdd_status fdd_power_spectrum_scaled(fdd_plan_t p, const void* in, float* out, void* stream) {
+  fdd_status s = check_ready(p, in, out);
+  if (s != FDD_OK) return s;
+  if (!p->scaled) return fail(FDD_E_UNSUPPORTED, "the plan was not made with FDD_PLAN_SCALED_DM");
+  hipStream_t st = (hipStream_t)stream;
+  mark(p, 0, st);
+  s = forward(p, in, st);
+  if (s != FDD_OK) return s;
+  hipError_t e;
+  if (p->sc_fmin > 0) {                      // low bins: exact, as fdd_power_spectrum
+    PhasorArgs all = phasor_args(p);
+    all.P = out;
+    if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
+      all.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
+    for (const Segment& sg : p->segs) {
+      PhasorArgs a = segment_args(p, all, sg, true);
+      a.n_bins = p->sc_fmin;
+      if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
+      else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+      else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+      else e = launch_phasor_valu(a, st);
+      if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+    }
+  }
+  ScaledArgs g;
+  g.X = (const float2*)(p->d_ws + p->ws.X);
+  g.ctab = (const uint4*)(p->d_ws + p->ws.ctab);
+  g.Q = (float*)(p->d_ws + p->ws.Q);
+  g.n_chan = p->desc.n_chan;
+  g.n_rows = p->desc.n_dm + 2 * kScaledHalo;
+  g.n_blocks = p->sc_blocks;
+  g.f_min = p->sc_fmin;
+  g.pitch = p->pitch;
+  g.q_pitch = (int64_t)p->sc_blocks * kScaledBlock;
+  e = launch_phasor_scaled(g, st);
+  if (e != hipSuccess) return hip_fail(e, "scaled-DM phasor-sum launch");
+  ResampleArgs r;
+  r.Q = g.Q;
+  r.P = out;
+  r.dms = (const double*)(p->d_ws + p->ws.dmv);
+  r.dm0 = p->grid_dm0;
+  r.step = p->grid_step;
+  r.n_dm = p->desc.n_dm;
+  r.n_rows = g.n_rows;
+  r.f_min = p->sc_fmin;
+  r.n_pow_bins = (int)(p->L / 2);
+  r.q_pitch = g.q_pitch;
+  e = launch_scaled_resample(r, st);
+  if (e != hipSuccess) return hip_fail(e, "DM resampling launch");
+  mark(p, 3, st);
+  mark(p, 4, st);
+  return FDD_OK;
+}
+
 }  // extern "C"

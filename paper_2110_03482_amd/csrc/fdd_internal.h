@@ -77,6 +77,35 @@ struct PhasorArgs {
   int n_fine = 0;
 };
 
+// Spin-frequency-scaled DMs (Eq. 8) for power spectra of one chunk.  Block b covers bins
+// f_min + 64 b .. + 63 with reference bin r = f_min + 64 b + 32; row q of the scaled grid has
+// DM'_q = DM_0 + (q - kScaledHalo) dDM and, at bin r, the phase increment inc_a + q inc_d
+// (64-bit turn fractions per bin, per channel in ctab).
+constexpr int kScaledBlock = 64;
+constexpr int kScaledHalo = 32;
+struct ScaledArgs {
+  const float2* X = nullptr;        // [n_chan][pitch] forward spectra
+  const uint4* ctab = nullptr;      // [n_chan] {inc_a.lo, inc_a.hi, inc_d.lo, inc_d.hi}
+  float* Q = nullptr;               // [n_rows][q_pitch] |sum_c W X|^2 from bin f_min on
+  int n_chan = 0;
+  int n_rows = 0;                   // n_dm + 2 kScaledHalo
+  int n_blocks = 0;
+  int f_min = 0;
+  int64_t pitch = 0;
+  int64_t q_pitch = 0;              // n_blocks * kScaledBlock
+};
+struct ResampleArgs {
+  const float* Q = nullptr;
+  float* P = nullptr;               // [n_dm][n_pow_bins]
+  const double* dms = nullptr;      // [n_dm] trial DMs
+  double dm0 = 0.0, step = 0.0;     // the uniform grid DM_0 + j dDM
+  int n_dm = 0;
+  int n_rows = 0;
+  int f_min = 0;
+  int n_pow_bins = 0;
+  int64_t q_pitch = 0;
+};
+
 // Brute-force time-domain dedispersion (Eq. 2) with nearest-sample delays.
 struct TddArgs {
   const uint8_t* in_u8 = nullptr;   // channel-major 8-bit input [n_chan][n_samp], or
@@ -202,6 +231,9 @@ int phasor_fac_fine(int n_chunks);
 hipError_t launch_phasor_fac(const PhasorArgs& a, int precision, hipStream_t st);
 int64_t phasor_fac_tiles(PhasorArgs* a, int precision);
 hipError_t launch_phasor_fac_grouped(int precision, bool persist, const Group<PhasorArgs>& g, hipStream_t st);
+// Spin-frequency-scaled DMs: the per-block matrix products and the resampling in DM.
+hipError_t launch_phasor_scaled(const ScaledArgs& a, hipStream_t st);
+hipError_t launch_scaled_resample(const ResampleArgs& a, hipStream_t st);
 
 // Grouped launches of the batched form.  Tiles per beam (for the prefix sums) come from the
 // *_tiles functions, which also fill a.n_dmt / a.n_bb where the kernel needs them.
@@ -241,6 +273,9 @@ struct WorkspaceLayout {
   size_t Z = 0, Z_bytes = 0;          // long transforms: float2 [max(n_chan, n_dm) * n_chunks][L/2]
   size_t l1 = 0, l1_bytes = 0;        // long transforms: per-series L1 sums
   size_t dtab = 0, dtab_bytes = 0;    // int [n_chan][n_dm] nearest-sample delays (time-domain path)
+  size_t ctab = 0, ctab_bytes = 0;    // scaled DMs: uint4 [n_chan] phase increments
+  size_t dmv = 0, dmv_bytes = 0;      // scaled DMs: double [n_dm] trial DMs
+  size_t Q = 0, Q_bytes = 0;          // scaled DMs: float [n_dm + 64][q_pitch]
   size_t total = 0;
 };
 
@@ -268,6 +303,10 @@ struct fdd_plan_s {
   std::vector<int32_t> ds;
   std::vector<fdd::Segment> segs;
   int64_t out_total = 0;
+  // spin-frequency-scaled DMs (FDD_PLAN_SCALED_DM)
+  bool scaled = false;
+  double grid_dm0 = 0.0, grid_step = 0.0;
+  int sc_fmin = 0, sc_blocks = 0;
   // stage timing: a ring of `prof_depth` calls x 5 events
   int prof_depth = 0;
   int64_t prof_calls = 0;               // calls recorded since the last read

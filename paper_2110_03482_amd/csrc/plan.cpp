@@ -129,6 +129,29 @@ void twiddle_table(int64_t L, std::vector<float2>* out) {
   }
 }
 
+// frac(tau / L) as a 64-bit turn fraction {lo, hi} (any sign of tau), evaluated in float64.
+static void turn_fraction(double tau, int lg, uint32_t* lo, uint32_t* hi) {
+  const double v = std::ldexp(tau, -lg);
+  const double fr = v - std::floor(v);
+  const double s = std::ldexp(fr, 32);
+  const double h = std::floor(s);
+  *hi = (uint32_t)std::min(h, 4294967295.0);
+  *lo = (uint32_t)std::min(std::floor(std::ldexp(s - h, 32)), 4294967295.0);
+}
+
+// Scaled-DM increments per channel: row q of the scaled grid has the delay
+// (DM_0 + (q - halo) dDM) kappa_c, i.e. the turn fraction per bin inc_a + q inc_d.
+static void scaled_table(const fdd_plan_s* p, std::vector<uint4>* out) {
+  out->resize(p->kappa.size());
+  const double first = p->grid_dm0 - (double)kScaledHalo * p->grid_step;
+  for (size_t c = 0; c < p->kappa.size(); ++c) {
+    uint4 e;
+    turn_fraction(first * p->kappa[c], p->log_len, &e.x, &e.y);
+    turn_fraction(p->grid_step * p->kappa[c], p->log_len, &e.z, &e.w);
+    (*out)[c] = e;
+  }
+}
+
 // Nearest-sample delays d = floor(tau + 1/2) of every (channel, DM), channel-major.
 static void delay_table(const fdd_plan_s* p, std::vector<int>* out) {
   const size_t nc = p->kappa.size(), nd = p->dms.size();
@@ -165,6 +188,14 @@ static fdd_status upload_tables(fdd_plan_s* p) {
   delay_table(p, &dt);
   e = hipMemcpy(p->d_ws + w.dtab, dt.data(), w.dtab_bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(delay table)");
+  if (p->scaled) {
+    std::vector<uint4> ct;
+    scaled_table(p, &ct);
+    e = hipMemcpy(p->d_ws + w.ctab, ct.data(), w.ctab_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(scaled-DM table)");
+    e = hipMemcpy(p->d_ws + w.dmv, p->dms.data(), w.dmv_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(trial DMs)");
+  }
   return FDD_OK;
 }
 
@@ -237,6 +268,16 @@ static fdd_status layout(fdd_plan_s* p) {
   if (!mul_ok((size_t)d.n_chan * (size_t)d.n_dm, sizeof(int), &w.dtab_bytes))
     return fail(FDD_E_NOMEM, "delay table size overflows");
   put(&w.dtab, w.dtab_bytes);
+  if (p->scaled) {
+    w.ctab_bytes = (size_t)d.n_chan * sizeof(uint4);
+    put(&w.ctab, w.ctab_bytes);
+    w.dmv_bytes = (size_t)d.n_dm * sizeof(double);
+    put(&w.dmv, w.dmv_bytes);
+    const size_t rows = (size_t)d.n_dm + 2 * kScaledHalo;
+    if (!mul_ok(rows * (size_t)p->sc_blocks * kScaledBlock, sizeof(float), &w.Q_bytes))
+      return fail(FDD_E_NOMEM, "scaled-DM buffer size overflows");
+    put(&w.Q, w.Q_bytes);
+  }
   w.total = off;
   return FDD_OK;
 }
@@ -453,6 +494,32 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
       p->kernel = d.precision == FDD_FP32 ? "fac_f32" : d.precision == FDD_FP16_SPLIT ? "fac_f16_split" : "fac_bf16_split";
     }
   }
+  // spin-frequency-scaled DMs (Eq. 8): first block whose rows stay within the halo
+  if (d.flags & FDD_PLAN_SCALED_DM) {
+    double dm0 = 0.0, step = 0.0;
+    const char* why = nullptr;
+    if (!d.single_chunk) why = "scaled DMs need a single-chunk plan";
+    else if (d.delay_mode != FDD_DELAY_EXACT) why = "scaled DMs need exact delays";
+    else if (L < 2 * kScaledBlock) why = "scaled DMs need chunk_len >= 128";
+    else if (d.n_dm > 65535) why = "scaled DMs take at most 65535 trial DMs";
+    else if (!uniform_grid(p->dms, &dm0, &step)) why = "scaled DMs need a uniform DM list (DM_0 + j dDM, n_dm >= 2)";
+    if (why != nullptr) {
+      delete p;
+      return fail(FDD_E_UNSUPPORTED, why);
+    }
+    p->scaled = true;
+    p->grid_dm0 = dm0;
+    p->grid_step = step;
+    double big = 0.0;
+    for (double v : p->dms) big = std::max(big, std::fabs(v));
+    // block starting at b (reference r = b + 32): rows move by at most big * 32 / (r dDM)
+    const double rmin = 32.0 * big / ((double)(kScaledHalo - 1) * step);
+    const double b = std::ceil(std::max(0.0, rmin - kScaledBlock / 2) / kScaledBlock) * kScaledBlock;
+    const int64_t half = L / 2;
+    // the first block always runs exactly: it holds bin 0 and its 8-bit zero-point restore
+    p->sc_fmin = (int)std::min<double>(std::max(b, (double)kScaledBlock), (double)half);
+    p->sc_blocks = (int)((half - p->sc_fmin + kScaledBlock - 1) / kScaledBlock);
+  }
   // spread of the nearest-sample delays over the DM tiles of the time-domain kernels
   for (int tile : {tdd_dm_tile(), tdd_tile64()}) {
     int span = 0;
@@ -508,6 +575,7 @@ fdd_status fdd_plan_info(fdd_plan_t p, fdd_plan_geometry* g) {
   g->workspace_bytes = p->ws.total;
   g->out_samples = p->out_total;
   g->n_segments = (int32_t)p->segs.size();
+  g->scaled_min_bin = p->scaled ? p->sc_fmin : 0;
   return FDD_OK;
 }
 

@@ -262,3 +262,52 @@ def test_smearing_factors():
     assert f[0] == 1 and f[-1] == 16 and np.all(np.diff(f) >= 0)          # ascending DMs: runs ascend
     with pytest.raises(fdd.FddError):
         fdd.fdd_smearing_factors(freqs, tsamp, dms, 3)
+
+
+# ----------------------------------------------------------------------------- scaled DMs (Sec. 2.3, Eq. 8)
+
+def _scaled_shift(dms, f_lo, f_hi, r):
+    """Largest |s* - j| over trials j and bins f_lo..f_hi of a block with reference bin r."""
+    step = (dms[-1] - dms[0]) / (dms.size - 1)
+    f = np.arange(f_lo, f_hi + 1, dtype=np.float64)
+    ss = (dms[:, None] * f[None, :] / r - dms[0]) / step
+    return float(np.abs(ss - np.arange(dms.size)[:, None]).max())
+
+
+@pytest.mark.parametrize("n_dm,dm0,dm1,L", [(4096, 0.0, 500.0, 1 << 22), (64, 0.0, 30.0, 4096),
+                                            (100, 20.0, 60.0, 8192), (3, 0.0, 1.0, 128)])
+def test_scaled_first_bin_rule(n_dm, dm0, dm1, L):
+    w = W.small_fp32()
+    dms = np.linspace(dm0, dm1, n_dm)
+    p = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, dms, L, L, single_chunk=True, input="f32", dry_run=True,
+                 power_only=True, scaled_dm=True)
+    fmin = int(p.geometry.scaled_min_bin)
+    assert fmin % 64 == 0 and 0 <= fmin <= L // 2
+    if fmin < L // 2:
+        assert _scaled_shift(dms, fmin, fmin + 63, fmin + 32) <= 31.0 + 1e-9
+    assert fmin >= min(64, L // 2)                      # bin 0 always runs exactly
+    if fmin > 64:
+        assert _scaled_shift(dms, fmin - 64, fmin - 1, fmin - 32) > 31.0
+    plain = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, dms, L, L, single_chunk=True, input="f32", dry_run=True,
+                     power_only=True)
+    assert plain.geometry.scaled_min_bin == 0
+    n_blocks = -(-(L // 2 - fmin) // 64)
+    assert p.geometry.workspace_bytes >= plain.geometry.workspace_bytes + (n_dm + 64) * n_blocks * 64 * 4
+
+
+def test_scaled_rejections():
+    w = W.small_fp32()
+    base = dict(input="f32", dry_run=True, scaled_dm=True)
+    cases = [
+        (dict(single_chunk=False), 20000, 4096, w.dms),                       # chunked
+        (dict(single_chunk=True, mode="round"), 4096, 4096, w.dms),          # nearest-sample delays
+        (dict(single_chunk=True), 64, 64, w.dms),                            # L below 128
+        (dict(single_chunk=True), 4096, 4096, np.array([0.0, 1.0, 3.0])),    # not uniform
+        (dict(single_chunk=True), 4096, 4096, np.array([5.0])),              # one DM
+    ]
+    for kw, ns, L, dms in cases:
+        args = dict(base)
+        args.update(kw)
+        with pytest.raises(fdd.FddError) as e:
+            fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, dms, ns, L, **args)
+        assert e.value.status == 3, kw

@@ -1,0 +1,121 @@
+"""GPU parity of power spectra with spin-frequency-scaled DMs (Sec. 2.3, Eq. 8) against the
+FP64 oracle's evaluation of the same approximation, and the approximation's own error against
+the exact power spectra.
+
+Parity bound: per DM row ||P - P_ref|| / ||P_ref|| <= 1e-5 (FP32 matrix products; the exact low
+bins follow the plan's precision, FP32 or FP16 split, both measured well inside 1e-5).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fdd = pytest.importorskip("paper_2110_03482_amd")
+
+TOL = 1e-5
+
+
+def rel(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return np.linalg.norm(y - ref, axis=-1) / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+
+
+def band(n_chan):
+    return W.channel_centres(1250.0, 1550.0, n_chan), 1550.0
+
+
+CASES = [
+    # label, n_chan, L, n_samp, n_dm, dm0, dm1, kind, precision
+    ("f32_64dm", 16, 4096, 4096, 64, 0.0, 30.0, "f32", "fp32"),
+    ("u8_full_zero_point", 24, 8192, 8192, 100, 20.0, 60.0, "u8", "fp32"),
+    ("f32_ragged_split_low", 12, 16384, 15000, 200, 0.0, 100.0, "f32", "fp16_split"),
+    ("f32_33dm", 7, 2048, 2048, 33, 0.0, 5.0, "f32", "fp32"),
+    ("f32_long_fft", 40, 1 << 17, 1 << 17, 300, 0.0, 200.0, "f32", "fp32"),
+    ("f32_all_exact", 5, 128, 100, 3, 0.0, 1.0, "f32", "fp32"),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_scaled_power_matches_oracle(case):
+    label, n_chan, L, n_samp, n_dm, dm0, dm1, kind, precision = case
+    freqs, ref = band(n_chan)
+    dms = np.linspace(dm0, dm1, n_dm)
+    x = W.gaussian_u8(n_samp, n_chan, 5) if kind == "u8" else W.gaussian_f32(n_chan, n_samp, 5)
+    print(f"{label}: {n_chan} ch, L={L}, n_samp={n_samp}, {n_dm} DMs {dm0}..{dm1}, {kind}, {precision}", flush=True)
+    with fdd.Plan(freqs, ref, 64e-6, dms, n_samp, L, single_chunk=True, input=kind, precision=precision,
+                  power_only=True, scaled_dm=True) as p:
+        f_min = int(p.geometry.scaled_min_bin)
+        xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        P = p.power_spectrum_scaled(xd)
+        E = p.power_spectrum(xd)
+        torch.cuda.synchronize()
+        P = P.cpu().numpy()
+        E = E.cpu().numpy()
+    ref_p = O.fdd_power_scaled(x, kind, dms, freqs, ref, 64e-6, L, f_min)
+    err = rel(P, ref_p)
+    print(f"{label}: f_min={f_min}, parity max rel err {err.max():.3e}", flush=True)
+    assert np.isfinite(P).all() and err.max() <= TOL
+    assert np.array_equal(P[:, :f_min], E[:, :f_min])            # low bins: the exact kernels
+    if f_min < L // 2:
+        approx = rel(P[:, f_min:], E[:, f_min:])
+        print(f"{label}: approximation vs exact power above f_min: median {np.median(approx):.3e}, "
+              f"max {approx.max():.3e}", flush=True)
+
+
+def test_scaled_rejected_without_flag():
+    freqs, ref = band(8)
+    dms = np.linspace(0.0, 10.0, 16)
+    with fdd.Plan(freqs, ref, 64e-6, dms, 4096, 4096, single_chunk=True, input="f32", power_only=True) as p:
+        with pytest.raises(fdd.FddError) as e:
+            p.power_spectrum_scaled(torch.zeros((8, 4096), dtype=torch.float32, device="cuda"))
+        assert e.value.status == 3
+
+
+@pytest.mark.slow
+def test_periodicity_workload_scaled_sampled():
+    """512 ch x 2^22 samples x 4096 DMs (0..500), pulsar at DM 57 (trial 467), P = 33 ms: parity
+    on sampled rows and bins, harmonic-summed detection, and the approximation error."""
+    w = W.periodicity()
+    x = W.gaussian_f32(w.n_chan, w.n_samp, 0)
+    tau57 = O.delays([57.0], w.freqs, w.ref_freq_mhz, w.tsamp_s)[0]
+    period = 33.0e-3 / w.tsamp_s
+    W.inject_periodic_f32(x, tau57, period, 0.03, 0.3)
+    f1 = w.n_samp / period
+    idx = []
+    for h in range(1, 9):
+        c = int(round(h * f1))
+        idx.extend(range(c - 2, c + 3))
+    rows = [0, 467, 4095]
+    rng = np.random.default_rng(1)
+    print("periodicity workload, scaled DMs: running", flush=True)
+    with fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, single_chunk=True, input="f32",
+                  precision="fp32", power_only=True, scaled_dm=True) as p:
+        f_min = int(p.geometry.scaled_min_bin)
+        bins = np.unique(np.concatenate([idx, rng.integers(0, w.chunk_len // 2, 1500),
+                                         np.arange(f_min - 3, f_min + 67), [w.chunk_len // 2 - 1]]))
+        xd = torch.from_numpy(x).cuda()
+        P = p.power_spectrum_scaled(xd)
+        torch.cuda.synchronize()
+        hs = P[:, idx].double().sum(dim=1).cpu().numpy()
+        Ps = P[rows].cpu().numpy()[:, bins]
+        E = p.power_spectrum(xd)
+        torch.cuda.synchronize()
+        es = E[:, idx].double().sum(dim=1).cpu().numpy()
+        Dr = (P[:, f_min:] - E[:, f_min:]).double().norm(dim=1) / E[:, f_min:].double().norm(dim=1)
+        Dr = Dr.cpu().numpy()
+    del P, E
+    print(f"f_min={f_min}; harmonic sums: scaled max at trial {int(np.argmax(hs))} ({hs.max():.4e}), "
+          f"exact max at {int(np.argmax(es))} ({es.max():.4e}), ratio at 467: {hs[467] / es[467]:.4f}", flush=True)
+    print(f"approximation vs exact above f_min, per-row rel L2: median {np.median(Dr):.3e}, max {Dr.max():.3e}",
+          flush=True)
+    assert int(np.argmax(hs)) == 467 and int(np.argmax(es)) == 467
+    ref = O.fdd_power_scaled(x, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, f_min,
+                             rows=rows, bins=bins)
+    err = rel(Ps, ref)
+    print(f"rows {rows}: parity rel err {err}", flush=True)
+    assert err.max() <= TOL

@@ -380,3 +380,77 @@ def test_injected_pulse_peaks_at_its_dm(mode):
               mode=mode)
     assert int(np.argmax(y[:, 1000])) == 30
     assert y[30, 1000] > 250.0
+
+
+# ----------------------------------------------------------------------------- scaled DMs, Sec. 2.3 / Eq. 8
+
+def _scaled_f_min(n_dm, dm_max, block=64, halo=32):
+    step = dm_max / (n_dm - 1)
+    rmin = 32.0 * dm_max / ((halo - 1) * step)
+    return max(block, int(np.ceil(max(0.0, rmin - block // 2) / block) * block))
+
+
+def test_scaled_phasor_is_the_exact_phasor_at_the_scaled_dm():
+    """Eq. 8: the reference bin's phasor at DM equals bin f's phasor (Eq. 4) at DM r / f."""
+    rng = np.random.default_rng(21)
+    L = 8192
+    freqs = np.sort(rng.uniform(1200.0, 1500.0, 9))
+    kap = O.kappa(freqs, 1500.0, 64e-6)
+    for r, f in [(100, 97), (2080, 2111), (3000, 2970), (4000, 4031)]:
+        dm = rng.uniform(0.0, 80.0, 5)
+        Ws = O.scaled_phasors(kap, dm, r, L)
+        for i in range(dm.size):
+            We = O.phasors((dm[i] * r / f) * kap, L, "exact")[:, f]
+            np.testing.assert_allclose(Ws[i], We, atol=1e-9)
+
+
+def test_scaled_equals_exact_at_reference_bins_and_below_f_min():
+    rng = np.random.default_rng(22)
+    L, n_chan, n_dm = 4096, 12, 40
+    freqs = np.sort(rng.uniform(1200.0, 1500.0, n_chan))
+    dms = np.linspace(3.0, 45.0, n_dm)
+    x = rng.standard_normal((n_chan, L))
+    f_min = _scaled_f_min(n_dm, 45.0) + 64          # some exact bins, then blocks
+    refs = np.arange(f_min + 32, L // 2, 64)
+    bins = np.concatenate([np.arange(0, f_min, 7), refs])
+    got = O.fdd_power_scaled(x, "f64", dms, freqs, 1500.0, 64e-6, L, f_min, bins=bins)
+    want = O.fdd_power(x, "f64", dms, freqs, 1500.0, 64e-6, L)[:, bins]
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-9 * want.max())
+
+
+def test_scaled_dm_independent_channel_is_exact_everywhere():
+    """A channel at the reference frequency has no delay: every scaled row equals |X|^2, so the
+    interpolation weights must sum to one at every bin."""
+    rng = np.random.default_rng(23)
+    L = 2048
+    x = rng.standard_normal((1, L))
+    dms = np.linspace(0.0, 30.0, 33)
+    got = O.fdd_power_scaled(x, "f64", dms, [1400.0], 1400.0, 64e-6, L, 64)
+    X = np.fft.rfft(x[0])[: L // 2]
+    np.testing.assert_allclose(got, np.broadcast_to(np.abs(X) ** 2, got.shape), rtol=1e-12)
+
+
+def test_scaled_two_channel_closed_form():
+    """A delta in a delay-free channel and in one with a small delay per unit DM: the exact power
+    is 2 + 2 cos(2 pi f DM kappa / L).  The scaled rows sample that cosine in DM at phase steps
+    below 0.01 rad, so linear resampling reproduces it to 1e-4, which fixes the direction of the
+    stretch (f / r), the reference bin and the row offset."""
+    L, n_dm = 4096, 64
+    x = np.zeros((2, L))
+    x[:, 0] = 1.0
+    ref_mhz = 1500.0
+    tsamp = 64e-6
+    dms = np.linspace(0.0, 60.0, n_dm)
+    step = dms[1] - dms[0]
+    # kappa with pi * step * kappa = 0.0095 rad per row at the highest reference bin
+    kap_target = 0.0095 / (np.pi * step)
+    nu = 1.0 / np.sqrt(kap_target * tsamp / 4.148808e3 + 1.0 / ref_mhz ** 2)
+    freqs = [ref_mhz, nu]
+    kap = O.kappa(freqs, ref_mhz, tsamp)[1]
+    f_min = _scaled_f_min(n_dm, 60.0)
+    got = O.fdd_power_scaled(x, "f64", dms, freqs, ref_mhz, tsamp, L, f_min)
+    f = np.arange(L // 2)
+    want = 2.0 + 2.0 * np.cos(2 * np.pi * f[None, :] * dms[:, None] * kap / L)
+    np.testing.assert_allclose(got, want, atol=1e-4)
+    # the approximation is not trivially exact here: rows move by whole steps within a block
+    assert np.abs(dms[-1] * (f_min + 1) / (f_min + 32) - dms[-1]) > step
