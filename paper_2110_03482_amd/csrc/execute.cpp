@@ -91,6 +91,13 @@ PhasorArgs segment_args(fdd_plan_t p, const PhasorArgs& all, const Segment& sg, 
   return a;
 }
 
+// The direct split kernels read X as split words: convert it once for all segments.
+hipError_t presplit(fdd_plan_t p, hipStream_t st) {
+  if (p->fac_fine > 0 || (p->kernel != "mfma_f16_split" && p->kernel != "mfma_bf16_split")) return hipSuccess;
+  return launch_split_x((float2*)(p->d_ws + p->ws.X), (const unsigned int*)(p->d_ws + p->ws.scale),
+                        p->desc.n_chan, (int)p->n_chunks, p->pitch, p->kernel == "mfma_bf16_split", st);
+}
+
 // Chunks k whose input samples [kS, kS + L) all lie inside the data.
 int full_chunks(fdd_plan_t p) {
   const int64_t n = p->desc.n_samp;
@@ -113,7 +120,8 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   PhasorArgs all = phasor_args(p);
   all.Yr = (float*)(p->d_ws + p->ws.Yr);
   all.Yi = (float*)(p->d_ws + p->ws.Yi);
-  hipError_t e;
+  hipError_t e = presplit(p, st);
+  if (e != hipSuccess) return hip_fail(e, "split launch");
   for (const Segment& sg : p->segs) {
     const PhasorArgs a = segment_args(p, all, sg, false);
     if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
@@ -201,7 +209,8 @@ fdd_status fdd_power_spectrum(fdd_plan_t p, const void* in, float* out, void* st
   // transform; the removed offset sits in bin 0 only, with phasor 1
   if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
     all.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
-  hipError_t e;
+  hipError_t e = presplit(p, st);
+  if (e != hipSuccess) return hip_fail(e, "split launch");
   for (const Segment& sg : p->segs) {
     const PhasorArgs a = segment_args(p, all, sg, true);
     if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
@@ -224,21 +233,6 @@ fdd_status fdd_power_spectrum_scaled(fdd_plan_t p, const void* in, float* out, v
   s = forward(p, in, st);
   if (s != FDD_OK) return s;
   hipError_t e;
-  if (p->sc_fmin > 0) {                      // low bins: exact, as fdd_power_spectrum
-    PhasorArgs all = phasor_args(p);
-    all.P = out;
-    if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
-      all.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
-    for (const Segment& sg : p->segs) {
-      PhasorArgs a = segment_args(p, all, sg, true);
-      a.n_bins = p->sc_fmin;
-      if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
-      else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
-      else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
-      else e = launch_phasor_valu(a, st);
-      if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
-    }
-  }
   ScaledArgs g;
   g.X = (const float2*)(p->d_ws + p->ws.X);
   g.ctab = (const uint4*)(p->d_ws + p->ws.ctab);
@@ -264,6 +258,25 @@ fdd_status fdd_power_spectrum_scaled(fdd_plan_t p, const void* in, float* out, v
   r.q_pitch = g.q_pitch;
   e = launch_scaled_resample(r, st);
   if (e != hipSuccess) return hip_fail(e, "DM resampling launch");
+  // low bins: exact, as fdd_power_spectrum, after the block products have read X (the split
+  // kernels convert it in place); their tiles end at f_min, a multiple of 64
+  if (p->sc_fmin > 0) {
+    e = presplit(p, st);
+    if (e != hipSuccess) return hip_fail(e, "split launch");
+    PhasorArgs all = phasor_args(p);
+    all.P = out;
+    if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
+      all.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
+    for (const Segment& sg : p->segs) {
+      PhasorArgs a = segment_args(p, all, sg, true);
+      a.n_bins = p->sc_fmin;
+      if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
+      else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+      else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+      else e = launch_phasor_valu(a, st);
+      if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+    }
+  }
   mark(p, 3, st);
   mark(p, 4, st);
   return FDD_OK;

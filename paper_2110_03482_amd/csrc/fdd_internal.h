@@ -222,7 +222,11 @@ hipError_t launch_c2r_long(const FftArgs& a, float2* work, float2* work2, hipStr
 constexpr int kMaxBlockLogN = 15;   // longest transform held by one workgroup: 2^15 complex points
 hipError_t launch_phasor_valu(const PhasorArgs& a, hipStream_t st);
 hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st);
+// The single-plan split kernels read X as split words: call launch_split_x on X first (in
+// place; X then no longer holds spectra).  The grouped split kernels read plain X.
 hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st);
+hipError_t launch_split_x(float2* X, const unsigned int* l1max, int n_chan, int n_chunks, int64_t pitch, bool bf16,
+                          hipStream_t st);
 bool phasor_mfma_f32_supported(int n_chunks);
 bool phasor_split_supported(int n_chunks);
 // DM-factorised kernels: fine DMs per coarse row for n_chunks chunks (0 if not supported), and

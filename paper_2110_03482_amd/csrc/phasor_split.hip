@@ -82,7 +82,17 @@ __device__ __forceinline__ uint32_t neg_second(uint32_t w) { return w ^ 0x800000
 __device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
 }  // namespace
 
-template <bool BF, int NT, int FB>
+// Per-chunk scale 2^(14 - ceil(log2 L1_k)) of the data operand (1 for an empty chunk).
+__device__ __forceinline__ float chunk_scale(unsigned int l1bits) {
+  const float l1 = __uint_as_float(l1bits);
+  int ex = 0;
+  (void)frexpf(l1, &ex);                  // l1 <= 2^ex
+  return l1 > 0.0f ? ldexpf(1.0f, 14 - ex) : 1.0f;
+}
+
+// PRE: X already holds, per complex value, the split words {hi, lo} of the scaled (Re, Im)
+// pair (k_split_x), so the staging only rearranges them.
+template <bool BF, int NT, int FB, bool PRE = false>
 __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int bid, const int n_dmt,
                                                   const int n_bb,
     const int tid) {
@@ -115,12 +125,7 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
     lhi[i] = make_uint4(0u, 0u, 0u, 0u);
     llo[i] = make_uint4(0u, 0u, 0u, 0u);
   }
-  if (tid < N) {
-    const float l1 = __uint_as_float(a.l1max[tid]);
-    int ex = 0;
-    (void)frexpf(l1, &ex);                // l1 <= 2^ex
-    colscale[tid] = l1 > 0.0f ? ldexpf(1.0f, 14 - ex) : 1.0f;
-  }
+  if (tid < N) colscale[tid] = chunk_scale(a.l1max[tid]);
   uint32_t* whi = reinterpret_cast<uint32_t*>(lhi);
   uint32_t* wlo = reinterpret_cast<uint32_t*>(llo);
 
@@ -151,7 +156,12 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         uint32_t h, l;                                    // (Re, Im) of X, scaled and split
-        split2<BF>((b ? pf[q].z : pf[q].x) * sk, (b ? pf[q].w : pf[q].y) * sk, &h, &l);
+        if constexpr (PRE) {
+          h = __float_as_uint(b ? pf[q].z : pf[q].x);
+          l = __float_as_uint(b ? pf[q].w : pf[q].y);
+        } else {
+          split2<BF>((b ? pf[q].z : pf[q].x) * sk, (b ? pf[q].w : pf[q].y) * sk, &h, &l);
+        }
         const int f = 2 * fp + b;
         const int w0 = f * BINW + k * ROWW + cl;          // column k: (Re, -Im)
         const int w1 = f * BINW + (k + N) * ROWW + cl;    // column k + N: (Im, Re)
@@ -280,7 +290,24 @@ __device__ __forceinline__ int linear_block_s() { return blockIdx.y * gridDim.x 
 
 template <bool BF, int NT, int FB>
 __global__ __launch_bounds__(256, 2) void k_phasor_split(PhasorArgs a, int n_dmt, int n_bb) {
-  phasor_split_body<BF, NT, FB>(a, linear_block_s(), n_dmt, n_bb, threadIdx.x);
+  phasor_split_body<BF, NT, FB, true>(a, linear_block_s(), n_dmt, n_bb, threadIdx.x);
+}
+
+// Scale and split X in place, once per call instead of once per DM tile: every complex value
+// (Re, Im) of chunk k becomes the two words {hi, lo} of split2(Re s_k, Im s_k).  Two values
+// per thread; rows are (channel, chunk) series of `pitch` bins.
+template <bool BF>
+__global__ __launch_bounds__(256) void k_split_x(float4* X, const unsigned int* l1max, int n_chunks, int64_t rows,
+                                                 int64_t pitch) {
+  const int64_t i = (int64_t)(blockIdx.y * gridDim.x + blockIdx.x) * 256 + threadIdx.x;
+  const int64_t per_row = pitch / 2;
+  if (i >= rows * per_row) return;
+  const float sk = chunk_scale(l1max[(i / per_row) % n_chunks]);
+  const float4 v = X[i];
+  uint32_t h0, l0, h1, l1;
+  split2<BF>(v.x * sk, v.y * sk, &h0, &l0);
+  split2<BF>(v.z * sk, v.w * sk, &h1, &l1);
+  X[i] = make_float4(__uint_as_float(h0), __uint_as_float(l0), __uint_as_float(h1), __uint_as_float(l1));
 }
 
 // Batched form: the tiles of every beam of the group, one per workgroup or persistent.
@@ -318,6 +345,20 @@ hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st) {
   if (!phasor_split_supported(a.n_chunks)) return hipErrorInvalidValue;
   if (a.P != nullptr && a.n_chunks != 1) return hipErrorInvalidValue;
   return bf16 ? launch_split_fb<true, 8>(a, st) : launch_split_fb<false, 8>(a, st);
+}
+
+hipError_t launch_split_x(float2* X, const unsigned int* l1max, int n_chan, int n_chunks, int64_t pitch, bool bf16,
+                          hipStream_t st) {
+  if (X == nullptr || l1max == nullptr || n_chan < 1 || n_chunks < 1 || pitch % 2 != 0) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)n_chan * n_chunks * (pitch / 2);
+  const dim3 grid = linear_grid((n + 255) / 256);
+  if (bf16)
+    hipLaunchKernelGGL(k_split_x<true>, grid, dim3(256), 0, st, (float4*)X, l1max, n_chunks,
+                       (int64_t)n_chan * n_chunks, pitch);
+  else
+    hipLaunchKernelGGL(k_split_x<false>, grid, dim3(256), 0, st, (float4*)X, l1max, n_chunks,
+                       (int64_t)n_chan * n_chunks, pitch);
+  return hipGetLastError();
 }
 
 namespace {
