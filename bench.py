@@ -224,12 +224,13 @@ def run_periodicity(args, dev) -> int:
                           "algorithmic_flops_per_launch": flops}
     plan.close()
     if args.precision == "all":
-        result["forms"] = {"scaled_dm_fp32": run_scaled(args, dev, w, xd, out, flops)}
+        result["forms"] = {f"scaled_dm_{p}": run_scaled(args, dev, w, xd, out, flops, p)
+                           for p in ("fp32", "fp16_split")}
     print(json.dumps(result), flush=True)
     return 0
 
 
-def run_scaled(args, dev, w, xd, exact, exact_flops) -> dict:
+def run_scaled(args, dev, w, xd, exact, exact_flops, precision: str) -> dict:
     """Spin-frequency-scaled DMs (Eq. 8) on the same input: time, matrix-core rate, and the
     approximation's error against the exact spectra in `exact`."""
     import torch
@@ -237,16 +238,17 @@ def run_scaled(args, dev, w, xd, exact, exact_flops) -> dict:
     import paper_2110_03482_amd as fdd
 
     plan = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, single_chunk=True,
-                    input="f32", precision="fp32", mode="exact", device=dev, power_only=True, scaled_dm=True)
+                    input="f32", precision=precision, mode="exact", device=dev, power_only=True, scaled_dm=True)
     g = plan.geometry
     f_min = int(g.scaled_min_bin)
     out = torch.empty_like(exact)
     plan.profile(args.steps)
-    ms = timed_steps(lambda: plan.power_spectrum_scaled(xd, out), args, "periodicity scaled DMs fp32")
+    ms = timed_steps(lambda: plan.power_spectrum_scaled(xd, out), args, f"periodicity scaled DMs {precision}")
     stage_ms, _ = plan.stage_ms()
     n_blocks = -(-(w.n_samp // 2 - f_min) // 64)
     gemm_flops = 8.0 * (w.n_dm + 64) * w.n_chan * n_blocks * 64     # matrix work of the block products
     achieved = gemm_flops / (stage_ms[2] * 1e-3) / 1e12
+    peak = PEAK["fp32_mfma_TFLOPs"] if precision == "fp32" else PEAK["fp16_mfma_TFLOPs"]
     err = []
     for r0 in range(0, w.n_dm, 256):
         a = out[r0: r0 + 256, f_min:].double()
@@ -261,9 +263,9 @@ def run_scaled(args, dev, w, xd, exact, exact_flops) -> dict:
     return {"value": w.n_dm * w.n_samp / (ms * 1e-3), "ms_per_step": ms,
             "stages_ms": {"forward_fft": stage_ms[1], "phasor_sum_power": stage_ms[2]},
             "f_min": f_min,
-            "roofline": {"kernel": "phasor_sum_scaled_f32 (block products + low bins + resampling)", "bound": "mfma",
-                         "achieved": achieved, "peak": PEAK["fp32_mfma_TFLOPs"], "unit": "TFLOP/s",
-                         "frac": achieved / PEAK["fp32_mfma_TFLOPs"], "traffic": None,
+            "roofline": {"kernel": f"phasor_sum_scaled_{precision} (block products + low bins + resampling)",
+                         "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved / peak, "traffic": None,
                          "algorithmic_flops_per_launch": gemm_flops},
             "exact_equivalent_tflops": exact_flops / (stage_ms[2] * 1e-3) / 1e12,
             "approx_rel_l2_vs_exact": {"median": float(np.median(err)), "max": float(err.max())},

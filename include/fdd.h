@@ -162,7 +162,8 @@ fdd_status fdd_power_spectrum(fdd_plan_t plan, const void* d_in, float* d_out, v
  * blocks of 64 with reference bin r = (first bin) + 32.  Within a block, row s of the scaled
  * grid (DM'_s = DM_0 + s dDM, s = -32 .. n_dm + 31) uses at bin f the DM DM'_s r / f, whose
  * phasor exp(+2 pi i r DM'_s kappa_c / L) does not depend on f, so the block's phasor sum is
- * one matrix product Q[s, f] = |sum_c W_r[s, c] X[c, f]|^2.  The power at trial DM_j and bin
+ * one matrix product Q[s, f] = |sum_c W_r[s, c] X[c, f]|^2 (in the plan's precision: FP32, or
+ * FP16/BF16 head+tail split).  The power at trial DM_j and bin
  * f is then resampled linearly in DM:
  *     s* = (DM_j f / r - DM_0) / dDM,  P[j, f] = (1 - w) Q[floor(s*), f] + w Q[floor(s*) + 1, f],
  * w = s* - floor(s*).  f_min is the smallest block start (at least 64) for which

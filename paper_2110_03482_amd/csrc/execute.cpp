@@ -232,9 +232,43 @@ fdd_status fdd_power_spectrum_scaled(fdd_plan_t p, const void* in, float* out, v
   mark(p, 0, st);
   s = forward(p, in, st);
   if (s != FDD_OK) return s;
-  hipError_t e;
+  const int prec = p->desc.precision;
+  const bool split = prec != FDD_FP32;
+  // low bins, exact as fdd_power_spectrum; their tiles end at f_min, a multiple of 64.  The
+  // direct split kernels read X split in place, the others read plain X: order the launches
+  // so that every kernel sees the form it reads.
+  const bool low_reads_split = p->fac_fine == 0 && (p->kernel == "mfma_f16_split" || p->kernel == "mfma_bf16_split");
+  auto low_bins = [&]() -> hipError_t {
+    if (p->sc_fmin <= 0) return hipSuccess;
+    PhasorArgs all = phasor_args(p);
+    all.P = out;
+    if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
+      all.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
+    for (const Segment& sg : p->segs) {
+      PhasorArgs a = segment_args(p, all, sg, true);
+      a.n_bins = p->sc_fmin;
+      hipError_t e;
+      if (p->fac_fine > 0) e = launch_phasor_fac(a, prec, st);
+      else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
+      else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+      else e = launch_phasor_valu(a, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  float2* X = (float2*)(p->d_ws + p->ws.X);
+  const unsigned int* l1max = (const unsigned int*)(p->d_ws + p->ws.scale);
+  hipError_t e = hipSuccess;
+  if (!low_reads_split) e = low_bins();
+  if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
+  if (split || low_reads_split) {
+    e = launch_split_x(X, l1max, p->desc.n_chan, (int)p->n_chunks, p->pitch, prec == FDD_BF16_SPLIT, st);
+    if (e != hipSuccess) return hip_fail(e, "split launch");
+  }
+  if (low_reads_split) e = low_bins();
+  if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
   ScaledArgs g;
-  g.X = (const float2*)(p->d_ws + p->ws.X);
+  g.X = X;
   g.ctab = (const uint4*)(p->d_ws + p->ws.ctab);
   g.Q = (float*)(p->d_ws + p->ws.Q);
   g.n_chan = p->desc.n_chan;
@@ -243,7 +277,7 @@ fdd_status fdd_power_spectrum_scaled(fdd_plan_t p, const void* in, float* out, v
   g.f_min = p->sc_fmin;
   g.pitch = p->pitch;
   g.q_pitch = (int64_t)p->sc_blocks * kScaledBlock;
-  e = launch_phasor_scaled(g, st);
+  e = launch_phasor_scaled(g, prec, l1max, st);
   if (e != hipSuccess) return hip_fail(e, "scaled-DM phasor-sum launch");
   ResampleArgs r;
   r.Q = g.Q;
@@ -258,25 +292,6 @@ fdd_status fdd_power_spectrum_scaled(fdd_plan_t p, const void* in, float* out, v
   r.q_pitch = g.q_pitch;
   e = launch_scaled_resample(r, st);
   if (e != hipSuccess) return hip_fail(e, "DM resampling launch");
-  // low bins: exact, as fdd_power_spectrum, after the block products have read X (the split
-  // kernels convert it in place); their tiles end at f_min, a multiple of 64
-  if (p->sc_fmin > 0) {
-    e = presplit(p, st);
-    if (e != hipSuccess) return hip_fail(e, "split launch");
-    PhasorArgs all = phasor_args(p);
-    all.P = out;
-    if (p->desc.input == FDD_IN_U8_TIME_MAJOR && p->desc.n_samp == p->L)
-      all.dc_add = 128.0f * (float)p->L * (float)p->desc.n_chan;
-    for (const Segment& sg : p->segs) {
-      PhasorArgs a = segment_args(p, all, sg, true);
-      a.n_bins = p->sc_fmin;
-      if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
-      else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
-      else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
-      else e = launch_phasor_valu(a, st);
-      if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
-    }
-  }
   mark(p, 3, st);
   mark(p, 4, st);
   return FDD_OK;

@@ -236,7 +236,9 @@ hipError_t launch_phasor_fac(const PhasorArgs& a, int precision, hipStream_t st)
 int64_t phasor_fac_tiles(PhasorArgs* a, int precision);
 hipError_t launch_phasor_fac_grouped(int precision, bool persist, const Group<PhasorArgs>& g, hipStream_t st);
 // Spin-frequency-scaled DMs: the per-block matrix products and the resampling in DM.
-hipError_t launch_phasor_scaled(const ScaledArgs& a, hipStream_t st);
+// precision FDD_FP32: plain X; split precisions: X split in place by launch_split_x, and the
+// per-chunk L1 maxima for the scale.
+hipError_t launch_phasor_scaled(const ScaledArgs& a, int precision, const unsigned int* l1max, hipStream_t st);
 hipError_t launch_scaled_resample(const ResampleArgs& a, hipStream_t st);
 
 // Grouped launches of the batched form.  Tiles per beam (for the prefix sums) come from the

@@ -25,61 +25,13 @@
 // columns b and b + B are NT/2 tiles apart).
 #include "device_math.h"
 #include "fdd_internal.h"
+#include "split_math.h"
 
 namespace fdd {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 constexpr int kXcds = 8;
 constexpr int kRows = 64;   // coarse rows per workgroup
-
-template <bool BF>
-struct Half;
-
-template <>
-struct Half<false> {
-  typedef half8 V8;
-  __device__ static __forceinline__ floatx4 mfma(V8 a, V8 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-  }
-};
-
-template <>
-struct Half<true> {
-  typedef bf16x8 V8;
-  __device__ static __forceinline__ floatx4 mfma(V8 a, V8 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-};
-
-typedef float float2v __attribute__((ext_vector_type(2)));
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
-
-// head/tail split of a pair, packed: first value in the low half of each word
-template <bool BF>
-__device__ __forceinline__ void split_pair(float x, float y, uint32_t* hi, uint32_t* lo) {
-  const float2v v = {x, y};
-  if constexpr (BF) {
-    const bf162v h = __builtin_convertvector(v, bf162v);
-    const float2v hb = __builtin_convertvector(h, float2v);
-    const float2v r = {x - hb[0], y - hb[1]};
-    *hi = __builtin_bit_cast(uint32_t, h);
-    *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf162v));
-  } else {
-    const half2v h = __builtin_convertvector(v, half2v);
-    const float2v hb = __builtin_convertvector(h, float2v);
-    const float2v r = {x - hb[0], y - hb[1]};
-    *hi = __builtin_bit_cast(uint32_t, h);
-    *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, half2v));
-  }
-}
-
-__device__ __forceinline__ uint32_t neg_hi(uint32_t w) { return w ^ 0x80000000u; }      // (x, y) -> (x, -y)
-__device__ __forceinline__ uint32_t swap16(uint32_t w) { return (w >> 16) | (w << 16); }  // (x, y) -> (y, x)
 
 // tile -> (bin block, coarse row tile).  Each XCD takes a contiguous range of bin blocks, in
 // order, and the row tiles of one bin block back to back: neighbouring bin blocks share cache
@@ -270,7 +222,7 @@ __device__ __forceinline__ void phasor_fac_f32_body(const PhasorArgs& a, const i
 template <bool BF, int NT, int FB>
 __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const int bid, const int n_at,
                                                       const int n_bb, const int tid) {
-  using H = Half<BF>;
+  using H = HalfMma<BF>;
   typedef typename H::V8 V8;
   constexpr int KC = 16;
   constexpr int NCOL = NT * 16;
@@ -297,12 +249,7 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
     lhi[i] = make_uint4(0u, 0u, 0u, 0u);
     llo[i] = make_uint4(0u, 0u, 0u, 0u);
   }
-  if (tid < N) {
-    const float l1 = __uint_as_float(a.l1max[tid]);
-    int ex = 0;
-    (void)frexpf(l1, &ex);                 // l1 <= 2^ex
-    colscale[tid] = l1 > 0.0f ? ldexpf(1.0f, 14 - ex) : 1.0f;
-  }
+  if (tid < N) colscale[tid] = chunk_scale(a.l1max[tid]);
   uint32_t* whi = reinterpret_cast<uint32_t*>(lhi);
   uint32_t* wlo = reinterpret_cast<uint32_t*>(llo);
 

@@ -20,10 +20,9 @@
 // so that the row tiles of one block run back to back on one XCD and share its L2.
 #include "device_math.h"
 #include "fdd_internal.h"
+#include "split_math.h"
 
 namespace fdd {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 namespace {
 constexpr int kXcds = 8;
@@ -145,6 +144,134 @@ __global__ __launch_bounds__(256) void k_phasor_scaled_f32(ScaledArgs a, int n_r
   }
 }
 
+// The same block products on the half-precision matrix cores, operands split into head and
+// tail (A_hi B_hi + A_hi B_lo + A_lo B_hi in FP32), from X already scaled and split in place
+// (launch_split_x).  K = 32 per product = 16 channels x (cos, sin): lane l holds the four
+// phasors of row l % 16 and channels 4 (l / 16) .. + 3 as packed (cos, sin) head and tail
+// pairs, and reads its B operand (the same four channels of column l % 16 of a tile) with one
+// 16-byte LDS load per tile and plane.
+template <bool BF>
+__global__ __launch_bounds__(256) void k_phasor_scaled_split(ScaledArgs a, int n_rt, const unsigned int* l1max) {
+  using H = HalfMma<BF>;
+  typedef typename H::V8 V8;
+  constexpr int KC = 16;                                  // channels per stage = one product's K
+  constexpr int ROWW = 20;                                // words per column: 16 channels + 4 padding
+  constexpr int PLANEW = kCols * ROWW;
+  __shared__ uint4 lhi2[2][PLANEW / 4];
+  __shared__ uint4 llo2[2][PLANEW / 4];
+  const int bid = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int xcd = bid % kXcds;
+  const int slot = bid / kXcds;
+  const int bb = (slot / n_rt) * kXcds + xcd;
+  const int rt = slot % n_rt;
+  if (bb >= a.n_blocks) return;                          // uniform per workgroup, before any barrier
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int f0 = a.f_min + bb * kScaledBlock;
+  const uint32_t ref = (uint32_t)(f0 + kScaledBlock / 2);
+  const float inv = 1.0f / chunk_scale(l1max[0]);
+
+  // staging element e = tid + 256 j: channel e / 32 of the stage, bins 2 (e % 32) and + 1;
+  // X holds the split words {hi, lo} of each scaled (Re, Im) pair
+  constexpr int PER = KC * (kScaledBlock / 2) / 256;
+  int ccl[PER], cbin[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j;
+    ccl[j] = e / (kScaledBlock / 2);
+    cbin[j] = 2 * (e % (kScaledBlock / 2));
+  }
+  uint4 pf[PER];
+  auto fetch = [&](int cb) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int c = cb + ccl[j];
+      pf[j] = c < a.n_chan ? *(const uint4*)(a.X + (int64_t)c * a.pitch + f0 + cbin[j]) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto deposit = [&](uint32_t* whi, uint32_t* wlo) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const uint32_t h = b ? pf[j].z : pf[j].x;
+        const uint32_t l = b ? pf[j].w : pf[j].y;
+        const int w0 = (cbin[j] + b) * ROWW + ccl[j];                  // column bin: (Re, -Im)
+        const int w1 = (kScaledBlock + cbin[j] + b) * ROWW + ccl[j];   // column 64 + bin: (Im, Re)
+        whi[w0] = neg_hi(h);
+        wlo[w0] = neg_hi(l);
+        whi[w1] = swap16(h);
+        wlo[w1] = swap16(l);
+      }
+    }
+  };
+
+  int q = rt * 64 + wave * 16 + (lane & 15);
+  if (q >= a.n_rows) q = a.n_rows - 1;                   // a clamped row's results are not stored
+  const uint64_t uq = (uint64_t)q;
+  const int cq = lane >> 4;
+
+  floatx4 acc[kNt];
+#pragma unroll
+  for (int nt = 0; nt < kNt; ++nt) acc[nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  fetch(0);
+  deposit(reinterpret_cast<uint32_t*>(lhi2[0]), reinterpret_cast<uint32_t*>(llo2[0]));
+  __syncthreads();
+  int it = 0;
+  for (int cb = 0; cb < a.n_chan; cb += KC, ++it) {
+    uint4 e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int c = cb + 4 * cq + k;
+      if (c >= a.n_chan) c = a.n_chan - 1;               // its data were staged as zeros
+      e[k] = a.ctab[c];
+    }
+    if (cb + KC < a.n_chan) fetch(cb + KC);              // in flight while this stage computes
+    uint32_t ah[4], al[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t inc_a = ((uint64_t)e[k].y << 32) | e[k].x;
+      const uint64_t inc_d = ((uint64_t)e[k].w << 32) | e[k].z;
+      const uint64_t inc = inc_a + uq * inc_d;
+      const PhaseInc pi = {(uint32_t)(inc >> 32), (uint32_t)inc};
+      float sn, cs;
+      sincos_turn(phase_at(pi, ref), &sn, &cs);
+      split_pair<BF>(cs, sn, &ah[k], &al[k]);
+    }
+    const V8 Ahi = __builtin_bit_cast(V8, make_uint4(ah[0], ah[1], ah[2], ah[3]));
+    const V8 Alo = __builtin_bit_cast(V8, make_uint4(al[0], al[1], al[2], al[3]));
+    const uint4* bhi = lhi2[it & 1];
+    const uint4* blo = llo2[it & 1];
+    const int base = ((lane & 15) * ROWW + 4 * cq) / 4;
+#pragma unroll
+    for (int nt = 0; nt < kNt; ++nt) {
+      const V8 Bh = __builtin_bit_cast(V8, bhi[base + 16 * nt * ROWW / 4]);
+      const V8 Bl = __builtin_bit_cast(V8, blo[base + 16 * nt * ROWW / 4]);
+      acc[nt] = H::mfma(Ahi, Bh, acc[nt]);
+      acc[nt] = H::mfma(Ahi, Bl, acc[nt]);
+      acc[nt] = H::mfma(Alo, Bh, acc[nt]);
+    }
+    // the other buffer was last read in the previous stage, which every wave has left
+    if (cb + KC < a.n_chan)
+      deposit(reinterpret_cast<uint32_t*>(lhi2[(it + 1) & 1]), reinterpret_cast<uint32_t*>(llo2[(it + 1) & 1]));
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int nt = 0; nt < kNt / 2; ++nt) {
+    const int bin = 16 * nt + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = rt * 64 + wave * 16 + 4 * (lane >> 4) + r;
+      if (row >= a.n_rows) continue;
+      const float yr = acc[nt][r] * inv, yi = acc[nt + kNt / 2][r] * inv;
+      a.Q[(int64_t)row * a.q_pitch + (int64_t)bb * kScaledBlock + bin] = fmaf(yr, yr, yi * yi);
+    }
+  }
+}
+
 // Linear resampling in DM: trial j at bin f reads the two scaled rows around
 // s* = (DM_j f / r - DM_0) / dDM.  Four bins per thread, one trial per grid row.
 __global__ __launch_bounds__(256) void k_scaled_resample(ResampleArgs a) {
@@ -181,16 +308,22 @@ __global__ __launch_bounds__(256) void k_scaled_resample(ResampleArgs a) {
     if (fb + i < a.n_pow_bins) dst[i] = out[i];
 }
 
-hipError_t launch_phasor_scaled(const ScaledArgs& a, hipStream_t st) {
+hipError_t launch_phasor_scaled(const ScaledArgs& a, int precision, const unsigned int* l1max, hipStream_t st) {
   if (a.n_blocks <= 0) return hipSuccess;
   if (a.n_rows < 2 || a.n_chan < 1 || a.X == nullptr || a.Q == nullptr || a.ctab == nullptr ||
-      a.q_pitch < (int64_t)a.n_blocks * kScaledBlock)
+      a.q_pitch < (int64_t)a.n_blocks * kScaledBlock || (precision != FDD_FP32 && l1max == nullptr))
     return hipErrorInvalidValue;
   const int n_rt = (a.n_rows + 63) / 64;
   const int64_t n_bb8 = ((int64_t)a.n_blocks + kXcds - 1) / kXcds * kXcds;
   const int64_t blocks = (int64_t)n_rt * n_bb8;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_phasor_scaled_f32, linear_grid(blocks), dim3(256), 0, st, a, n_rt);
+  const dim3 grid = linear_grid(blocks);
+  if (precision == FDD_FP32)
+    hipLaunchKernelGGL(k_phasor_scaled_f32, grid, dim3(256), 0, st, a, n_rt);
+  else if (precision == FDD_FP16_SPLIT)
+    hipLaunchKernelGGL(k_phasor_scaled_split<false>, grid, dim3(256), 0, st, a, n_rt, l1max);
+  else
+    hipLaunchKernelGGL(k_phasor_scaled_split<true>, grid, dim3(256), 0, st, a, n_rt, l1max);
   return hipGetLastError();
 }
 

@@ -20,75 +20,13 @@
 // of the next 16 channels is prefetched into registers while the current one is in use.
 #include "device_math.h"
 #include "fdd_internal.h"
+#include "split_math.h"
 
 namespace fdd {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
 namespace {
 constexpr int kXcds = 8;
-
-template <bool BF>
-struct HalfOps;
-
-template <>
-struct HalfOps<false> {
-  typedef half8 V8;
-  __device__ static __forceinline__ uint16_t bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
-  __device__ static __forceinline__ float value(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
-  __device__ static __forceinline__ floatx4 mfma(V8 a, V8 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-  }
-};
-
-template <>
-struct HalfOps<true> {
-  typedef bf16x8 V8;
-  __device__ static __forceinline__ uint16_t bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
-  __device__ static __forceinline__ float value(uint16_t b) { return (float)__builtin_bit_cast(__bf16, b); }
-  __device__ static __forceinline__ floatx4 mfma(V8 a, V8 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-};
-
-typedef float float2v __attribute__((ext_vector_type(2)));
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
-
-// Head/tail split of a pair (a, b): hi = (half(a), half(b)), lo = (half(a - hi_a), half(b - hi_b)),
-// each returned as one 32-bit word (first value in the low half).
-template <bool BF>
-__device__ __forceinline__ void split2(float a, float b, uint32_t* hi, uint32_t* lo) {
-  const float2v x = {a, b};
-  if constexpr (BF) {
-    const bf162v h = __builtin_convertvector(x, bf162v);
-    const float2v hb = __builtin_convertvector(h, float2v);
-    const float2v r = {a - hb[0], b - hb[1]};
-    *hi = __builtin_bit_cast(uint32_t, h);
-    *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf162v));
-  } else {
-    const half2v h = __builtin_convertvector(x, half2v);
-    const float2v hb = __builtin_convertvector(h, float2v);
-    const float2v r = {a - hb[0], b - hb[1]};
-    *hi = __builtin_bit_cast(uint32_t, h);
-    *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, half2v));
-  }
-}
-
-// (x, y) -> (x, -y) and (x, y) -> (y, x) on packed half pairs (exact).
-__device__ __forceinline__ uint32_t neg_second(uint32_t w) { return w ^ 0x80000000u; }
-__device__ __forceinline__ uint32_t swap_halves(uint32_t w) { return (w >> 16) | (w << 16); }
 }  // namespace
-
-// Per-chunk scale 2^(14 - ceil(log2 L1_k)) of the data operand (1 for an empty chunk).
-__device__ __forceinline__ float chunk_scale(unsigned int l1bits) {
-  const float l1 = __uint_as_float(l1bits);
-  int ex = 0;
-  (void)frexpf(l1, &ex);                  // l1 <= 2^ex
-  return l1 > 0.0f ? ldexpf(1.0f, 14 - ex) : 1.0f;
-}
 
 // PRE: X already holds, per complex value, the split words {hi, lo} of the scaled (Re, Im)
 // pair (k_split_x), so the staging only rearranges them.
@@ -96,7 +34,7 @@ template <bool BF, int NT, int FB, bool PRE = false>
 __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int bid, const int n_dmt,
                                                   const int n_bb,
     const int tid) {
-  using H = HalfOps<BF>;
+  using H = HalfMma<BF>;
   typedef typename H::V8 V8;
   constexpr int KC = 16;                 // channels per LDS stage = one MFMA contraction step
   constexpr int NCOL = NT * 16;
@@ -160,15 +98,15 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
           h = __float_as_uint(b ? pf[q].z : pf[q].x);
           l = __float_as_uint(b ? pf[q].w : pf[q].y);
         } else {
-          split2<BF>((b ? pf[q].z : pf[q].x) * sk, (b ? pf[q].w : pf[q].y) * sk, &h, &l);
+          split_pair<BF>((b ? pf[q].z : pf[q].x) * sk, (b ? pf[q].w : pf[q].y) * sk, &h, &l);
         }
         const int f = 2 * fp + b;
         const int w0 = f * BINW + k * ROWW + cl;          // column k: (Re, -Im)
         const int w1 = f * BINW + (k + N) * ROWW + cl;    // column k + N: (Im, Re)
-        whi[w0] = neg_second(h);
-        wlo[w0] = neg_second(l);
-        whi[w1] = swap_halves(h);
-        wlo[w1] = swap_halves(l);
+        whi[w0] = neg_hi(h);
+        wlo[w0] = neg_hi(l);
+        whi[w1] = swap16(h);
+        wlo[w1] = swap16(l);
       }
     }
   };
@@ -228,7 +166,7 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
       uint32_t ah[4], al[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        split2<BF>(w[q].x, w[q].y, &ah[q], &al[q]);
+        split_pair<BF>(w[q].x, w[q].y, &ah[q], &al[q]);
         w[q] = cmul(w[q], st[q]);
       }
       const V8 Ahi = __builtin_bit_cast(V8, make_uint4(ah[0], ah[1], ah[2], ah[3]));
@@ -305,8 +243,8 @@ __global__ __launch_bounds__(256) void k_split_x(float4* X, const unsigned int* 
   const float sk = chunk_scale(l1max[(i / per_row) % n_chunks]);
   const float4 v = X[i];
   uint32_t h0, l0, h1, l1;
-  split2<BF>(v.x * sk, v.y * sk, &h0, &l0);
-  split2<BF>(v.z * sk, v.w * sk, &h1, &l1);
+  split_pair<BF>(v.x * sk, v.y * sk, &h0, &l0);
+  split_pair<BF>(v.z * sk, v.w * sk, &h1, &l1);
   X[i] = make_float4(__uint_as_float(h0), __uint_as_float(l0), __uint_as_float(h1), __uint_as_float(l1));
 }
 

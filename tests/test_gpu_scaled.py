@@ -2,8 +2,9 @@
 FP64 oracle's evaluation of the same approximation, and the approximation's own error against
 the exact power spectra.
 
-Parity bound: per DM row ||P - P_ref|| / ||P_ref|| <= 1e-5 (FP32 matrix products; the exact low
-bins follow the plan's precision, FP32 or FP16 split, both measured well inside 1e-5).
+Parity bound: per DM row ||P - P_ref|| / ||P_ref|| <= 1e-5 for FP32 and FP16 split, 1e-4 for BF16
+split (about 16 significant bits in head + tail), as for the exact kernels; the block products
+and the exact low bins both run in the plan's precision.
 """
 import numpy as np
 import pytest
@@ -17,6 +18,7 @@ torch = pytest.importorskip("torch")
 fdd = pytest.importorskip("paper_2110_03482_amd")
 
 TOL = 1e-5
+TOLS = {"fp32": 1e-5, "fp16_split": 1e-5, "bf16_split": 1e-4}
 
 
 def rel(y, ref):
@@ -37,6 +39,8 @@ CASES = [
     ("f32_33dm", 7, 2048, 2048, 33, 0.0, 5.0, "f32", "fp32"),
     ("f32_long_fft", 40, 1 << 17, 1 << 17, 300, 0.0, 200.0, "f32", "fp32"),
     ("f32_all_exact", 5, 128, 100, 3, 0.0, 1.0, "f32", "fp32"),
+    ("u8_bf16_split", 20, 8192, 8192, 90, 5.0, 40.0, "u8", "bf16_split"),
+    ("f32_fp16_split_long", 33, 1 << 17, 1 << 17, 150, 0.0, 120.0, "f32", "fp16_split"),
 ]
 
 
@@ -59,7 +63,7 @@ def test_scaled_power_matches_oracle(case):
     ref_p = O.fdd_power_scaled(x, kind, dms, freqs, ref, 64e-6, L, f_min)
     err = rel(P, ref_p)
     print(f"{label}: f_min={f_min}, parity max rel err {err.max():.3e}", flush=True)
-    assert np.isfinite(P).all() and err.max() <= TOL
+    assert np.isfinite(P).all() and err.max() <= TOLS[precision]
     assert np.array_equal(P[:, :f_min], E[:, :f_min])            # low bins: the exact kernels
     if f_min < L // 2:
         approx = rel(P[:, f_min:], E[:, f_min:])
