@@ -273,39 +273,51 @@ __global__ __launch_bounds__(256) void k_phasor_scaled_split(ScaledArgs a, int n
 }
 
 // Linear resampling in DM: trial j at bin f reads the two scaled rows around
-// s* = (DM_j f / r - DM_0) / dDM.  Four bins per thread, one trial per grid row.
+// s* = (DM_j f / r - DM_0) / dDM.  A thread takes four consecutive bins (one block, one r) of
+// kResampleRows consecutive trials, whose scaled rows overlap, so each row comes from memory
+// about once.  s* is linear in f within a block: s* = f DM_j / (r dDM) - DM_0 / dDM.
+constexpr int kResampleRows = 8;
+
 __global__ __launch_bounds__(256) void k_scaled_resample(ResampleArgs a) {
-  const int j = (int)blockIdx.y;
+  const int j0 = (int)blockIdx.y * kResampleRows;
   const int64_t fb = (int64_t)a.f_min + 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
   if (fb >= a.n_pow_bins) return;
-  const double dm = a.dms[j];
-  float out[4];
+  const int64_t col0 = fb - a.f_min;
+  const int64_t ref = a.f_min + col0 / kScaledBlock * kScaledBlock + kScaledBlock / 2;
+  const double off = a.dm0 / a.step;
+  for (int jj = 0; jj < kResampleRows; ++jj) {
+    const int j = j0 + jj;
+    if (j >= a.n_dm) break;
+    const double slope = a.dms[j] / ((double)ref * a.step);
+    float out[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t f = fb + i;
-    out[i] = 0.0f;
-    if (f >= a.n_pow_bins) continue;
-    const int64_t col = f - a.f_min;
-    const int64_t ref = a.f_min + col / kScaledBlock * kScaledBlock + kScaledBlock / 2;
-    const double ss = (dm * (double)f / (double)ref - a.dm0) / a.step;
-    const double fl = floor(ss);
-    int64_t q0 = (int64_t)fl + kScaledHalo;
-    double w = ss - fl;
-    if (q0 < 0) {                                          // outside the planned halo: clamp
-      q0 = 0;
-      w = 0.0;
-    } else if (q0 > a.n_rows - 2) {
-      q0 = a.n_rows - 2;
-      w = 1.0;
+    for (int i = 0; i < 4; ++i) {
+      out[i] = 0.0f;
+      if (fb + i >= a.n_pow_bins) continue;
+      const double ss = fma(slope, (double)(fb + i), -off);
+      const double fl = floor(ss);
+      int64_t q0 = (int64_t)fl + kScaledHalo;
+      double w = ss - fl;
+      if (q0 < 0) {                                        // outside the planned halo: clamp
+        q0 = 0;
+        w = 0.0;
+      } else if (q0 > a.n_rows - 2) {
+        q0 = a.n_rows - 2;
+        w = 1.0;
+      }
+      const float* src = a.Q + q0 * a.q_pitch + col0 + i;
+      const float wf = (float)w;
+      out[i] = fmaf(wf, src[a.q_pitch], (1.0f - wf) * src[0]);
     }
-    const float* src = a.Q + q0 * a.q_pitch + col;
-    const float wf = (float)w;
-    out[i] = fmaf(wf, src[a.q_pitch], (1.0f - wf) * src[0]);
-  }
-  float* dst = a.P + (int64_t)j * a.n_pow_bins + fb;
+    float* dst = a.P + (int64_t)j * a.n_pow_bins + fb;
+    if (fb + 4 <= a.n_pow_bins) {
+      *(float4*)dst = make_float4(out[0], out[1], out[2], out[3]);
+    } else {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (fb + i < a.n_pow_bins) dst[i] = out[i];
+      for (int i = 0; i < 4; ++i)
+        if (fb + i < a.n_pow_bins) dst[i] = out[i];
+    }
+  }
 }
 
 hipError_t launch_phasor_scaled(const ScaledArgs& a, int precision, const unsigned int* l1max, hipStream_t st) {
@@ -334,8 +346,9 @@ hipError_t launch_scaled_resample(const ResampleArgs& a, hipStream_t st) {
       !(a.step > 0.0))
     return hipErrorInvalidValue;
   const int64_t gx = (bins + 4 * 256 - 1) / (4 * 256);
-  if (gx > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_scaled_resample, dim3((unsigned)gx, (unsigned)a.n_dm), dim3(256), 0, st, a);
+  if (gx > 0x7fffffff || (a.n_pow_bins - a.f_min) % 4 != 0) return hipErrorInvalidValue;
+  const unsigned gy = (unsigned)((a.n_dm + kResampleRows - 1) / kResampleRows);
+  hipLaunchKernelGGL(k_scaled_resample, dim3((unsigned)gx, gy), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
