@@ -47,6 +47,37 @@ __global__ __launch_bounds__(256) void k_transpose_u8(const uint8_t* __restrict_
   }
 }
 
+// The same for n_samp and n_chan multiples of 64, moving 4-byte words: a thread loads 4
+// channels of one sample and stores 4 samples of one channel, gathered from the tile with byte
+// permutes.
+__global__ __launch_bounds__(256) void k_transpose_u8_w(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                        int64_t n_samp, int n_chan) {
+  __shared__ uint32_t tile[64][17];                 // [sample][4-channel word], padded row
+  const int64_t t0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  const int64_t wrow = n_chan / 4;                  // words per input row
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int idx = tid + 256 * e;
+    const int i = idx >> 4, k = idx & 15;           // sample i, channel word k
+    tile[i][k] = in[(t0 + i) * wrow + c0 / 4 + k];
+  }
+  __syncthreads();
+  const int64_t wcol = n_samp / 4;                  // words per output row
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int idx = tid + 256 * e;
+    const int c = idx >> 4, g = idx & 15;           // channel c, samples 4g .. 4g + 3
+    const int k = c >> 2, sh = 8 * (c & 3);
+    const uint32_t b0 = (tile[4 * g][k] >> sh) & 0xffu;
+    const uint32_t b1 = (tile[4 * g + 1][k] >> sh) & 0xffu;
+    const uint32_t b2 = (tile[4 * g + 2][k] >> sh) & 0xffu;
+    const uint32_t b3 = (tile[4 * g + 3][k] >> sh) & 0xffu;
+    out[(int64_t)(c0 + c) * wcol + t0 / 4 + g] = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+  }
+}
+
 // ----------------------------------------------------------------------------- forward
 
 // Sum over the workgroup (any size up to 1024); lds needs blockDim.x / 64 floats.
@@ -547,7 +578,11 @@ hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t st) {
 
 hipError_t launch_transpose_u8(const uint8_t* in, uint8_t* out, int64_t n_samp, int n_chan, hipStream_t st) {
   dim3 grid((unsigned)((n_samp + 63) / 64), (unsigned)((n_chan + 63) / 64));
-  hipLaunchKernelGGL(k_transpose_u8, grid, dim3(256), 0, st, in, out, n_samp, n_chan);
+  const bool words = n_samp % 64 == 0 && n_chan % 64 == 0 && ((uintptr_t)in & 3u) == 0 && ((uintptr_t)out & 3u) == 0;
+  if (words)
+    hipLaunchKernelGGL(k_transpose_u8_w, grid, dim3(256), 0, st, (const uint32_t*)in, (uint32_t*)out, n_samp, n_chan);
+  else
+    hipLaunchKernelGGL(k_transpose_u8, grid, dim3(256), 0, st, in, out, n_samp, n_chan);
   return hipGetLastError();
 }
 
