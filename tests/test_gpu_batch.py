@@ -315,3 +315,50 @@ def test_batch_shared_phasors(precision):
     for (w, _, _, _), y, s1 in zip(beams, ys, singles):
         assert rel_err(y, s1).max() <= bound, w.name
     check_oracle(beams, ys, bound)
+
+
+@pytest.mark.slow
+def test_batched_workload_full_size_sampled_rows():
+    """The 32-beam batched workload at full size, as bench.py times it (seed 0, FP32,
+    autotuned, graph): every pulse found at its DM, and sampled rows of one beam of each
+    phasor shape class (chunk-column tiles, factorised or not) against the oracle."""
+    beams = W.batched_beams(32, seed=0)
+    xs = []
+    for w, pulse_dm, t0 in beams:
+        x = W.gaussian_f32(w.n_chan, w.n_samp, w.seed)
+        offs = O.nearest_sample(O.delays([pulse_dm], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
+        W.inject_pulse_f32(x, offs, t0, 5.0, circular=False)
+        xs.append(x)
+    print("batched workload: inputs generated", flush=True)
+    plans = [fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, input="f32",
+                      precision="fp32", workspace=False) for w, _, _ in beams]
+    # one beam per chunk count (which fixes its shape class), the largest first
+    pick = {}
+    for i, p in enumerate(plans):
+        n = int(p.geometry.n_chunks)
+        if n not in pick or beams[i][0].n_chan * beams[i][0].n_samp > beams[pick[n]][0].n_chan * beams[pick[n]][0].n_samp:
+            pick[n] = i
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    outs = [torch.empty((w.n_dm, w.n_samp), dtype=torch.float32, device="cuda") for w, _, _ in beams]
+    with fdd.Batch(plans) as b:
+        b.execute(xd, outs)
+        b.execute(xd, outs)                      # a graph replay
+        torch.cuda.synchronize()
+        print(f"batched workload: {b.n_waves} waves; classes "
+              f"{[(c['key'], c['choice']) for c in b.describe()['classes']]}", flush=True)
+    hits = 0
+    for (w, pulse_dm, t0), y in zip(beams, outs):
+        peak = int(torch.argmax(y[:, t0 - 2:t0 + 3].amax(dim=1)).item())
+        hits += abs(w.dms[peak] - pulse_dm) <= 2.0 * (w.dms[1] - w.dms[0]) + 1.0
+    assert hits == len(beams)
+    for n, i in sorted(pick.items()):
+        w, pulse_dm, t0 = beams[i]
+        trial = int(np.argmin(np.abs(w.dms - pulse_dm)))
+        rows = sorted({0, trial, w.n_dm - 1})
+        yr = outs[i][rows].cpu().numpy()
+        ref = O.fdd(xs[i], "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, mode="exact", rows=rows)
+        err = rel_err(yr, ref)
+        print(f"{w.name} ({n} chunks) rows {rows}: rel err {err}", flush=True)
+        assert err.max() <= TOL
+    for p in plans:
+        p.close()
