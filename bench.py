@@ -479,9 +479,13 @@ def main() -> int:
         peak = {"fp32": PEAK["fp32_mfma_TFLOPs"], "fp16_split": PEAK["fp16_mfma_TFLOPs"],
                 "bf16_split": PEAK["bf16_mfma_TFLOPs"]}[form["precision"]]
         wl = w.name + f"_{args.mode}_{form['precision']}" + ("" if form["factors"] is None else "_downsampled")
-        return {"kernel": f"phasor_sum_{form['kernel']}", "bound": "alu" if form["kernel"] == "valu" else "mfma",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic(form["kernel"], wl), "algorithmic_flops_per_launch": flops}
+        r = {"kernel": f"phasor_sum_{form['kernel']}", "bound": "alu" if form["kernel"] == "valu" else "mfma",
+             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+             "traffic": measured_traffic(form["kernel"], wl), "algorithmic_flops_per_launch": flops}
+        if form["precision"] != "fp32":
+            # each useful complex MAC costs three half-precision products (hi.hi, hi.lo, lo.hi)
+            r["matrix_work_frac"] = 3.0 * achieved / peak
+        return r
 
     # errors of each form against the FP64 oracle on this workload, measured by the parity tests
     stated_err = {"fp32": 4e-7, "fp16_split": 4e-8, "bf16_split": 2e-7}
