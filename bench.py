@@ -488,7 +488,7 @@ def main() -> int:
         return r
 
     # errors of each form against the FP64 oracle on this workload, measured by the parity tests
-    stated_err = {"fp32": 4e-7, "fp16_split": 4e-8, "bf16_split": 2e-7}
+    stated_err = {"fp32": 4e-7, "fp16_split": 4e-8, "bf16_split": 5e-8}
     result = {
         "metric": METRIC,
         "value": main_form["value"],

@@ -108,17 +108,18 @@ def test_split_power(precision):
     assert err.max() <= 2 * BOUND[precision]
 
 
-def test_split_paper_shaped_rows():
+@pytest.mark.parametrize("precision", ["fp16_split", "bf16_split"])
+def test_split_paper_shaped_rows(precision):
     w = W.paper_shaped_u8()
     x = W.gaussian_u8(w.n_samp, w.n_chan, 0)
     for dm, t0 in ((100.0, 1 << 18), (450.0, 1 << 19), (900.0, 3 << 18)):
         offs = O.nearest_sample(O.delays([dm], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
         W.inject_pulse_u8(x, offs, t0, 80.0)
-    y, kernel = run_gpu(w, x, "exact", "fp16_split")
-    rows = [3, 921]
+    y, kernel = run_gpu(w, x, "exact", precision)
+    rows = [3, 921, 2047]
     ref = O.fdd(x, "u8", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, mode="exact", rows=rows)
     err = rel_err(y[rows], ref)
-    print(f"fp16_split paper-shaped rows {rows}: kernel={kernel} rel err {err}")
-    assert err.max() <= BOUND["fp16_split"]
+    print(f"{precision} paper-shaped rows {rows}: kernel={kernel} rel err {err}")
+    assert err.max() <= BOUND[precision]
     for trial, t0 in ((205, 1 << 18), (921, 1 << 19), (1842, 3 << 18)):
         assert abs(int(np.argmax(y[:, t0 - 2: t0 + 3].max(axis=1))) - trial) <= 2
