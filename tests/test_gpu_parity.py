@@ -118,6 +118,8 @@ CHUNKED = [
     (32, 30000, 130, 4096, "u8", 25.0),   # (MFMA, 3 DM tiles)
     (40, 9000, 33, 1024, "f32", 3.0),     # short chunks, many of them (MFMA, 2 column tiles)
     (5, 700, 3, 64, "f32", 0.05),         # shortest transform
+    (16, 20000, 700, 2048, "u8", 8.0),    # 700 DMs, 11 chunks (MFMA, 11 DM tiles)
+    (12, 9000, 1100, 1024, "f32", 4.0),   # 1100 DMs, 10 chunks (MFMA, ragged last DM tile)
 ]
 
 
