@@ -74,17 +74,18 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
   }
 
   // Staging map, fixed for all channel blocks: element e = tid + 256 j is the float4 of bins
-  // (2 fp, 2 fp + 1) of chunk k of channel cl of the block.
-  int goff[PER], loff[PER], kk[PER], ccl[PER];
+  // (2 fp, 2 fp + 1) of chunk k of channel cl of the block.  The chunk varies fastest, so the
+  // LDS stores of a wave fall in consecutive words of a bin row; bin pairs are 2 NCOL words
+  // apart, a multiple of the 32 banks, and varying them first put 4 lanes on each bank.
+  int goff[PER], loff[PER], ccl[PER];
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int e = tid + 256 * j;
-    const int fp = e % (FB / 2);
-    const int k = (e / (FB / 2)) % N;
+    const int k = e % N;
+    const int fp = (e / N) % (FB / 2);
     const int cl = e / ((FB / 2) * N);
     goff[j] = (cl * N + k) * (int)a.pitch + fb0 + 2 * fp;     // in float2 units, < 2^31 for N <= 24
     loff[j] = cl * CST + 2 * fp * NCOL + k;
-    kk[j] = k;
     ccl[j] = e < nel ? cl : KC;                                 // KC marks "no element"
   }
   float4 pf[PER];
