@@ -189,6 +189,19 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
             acc[m][f][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wi[f], pi[f * NCOL + 16 * nt], acc[m][f][nt], 0, 0, 0);
       }
     }
+    if constexpr (FB == 8 && MW == 1) {
+      // Scheduling only: keep two B-operand reads (ds_read2, two MFMAs each) in flight ahead of
+      // the matrix instructions; left alone, the scheduler waits for each read right before
+      // its two MFMAs.  The other tile shapes lose occupancy to the extra registers.
+      constexpr int kReads = (KC / 4) * FB * NT;
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);      // DS reads
+#pragma unroll
+      for (int i = 0; i < kReads - 2; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);    // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+    }
     // the other buffer was last read in the previous group, which every wave has left
     if (cb + KC < a.n_chan) deposit(bre2[(it + 1) & 1], bim2[(it + 1) & 1]);
     __syncthreads();
