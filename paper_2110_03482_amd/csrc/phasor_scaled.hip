@@ -124,6 +124,18 @@ __global__ __launch_bounds__(256) void k_phasor_scaled_f32(ScaledArgs a, int n_r
 #pragma unroll
       for (int nt = 0; nt < kNt; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(sn, pm[16 * nt], acc[nt], 0, 0, 0);
     }
+    {
+      // Scheduling only: keep two B-operand reads (ds_read2, two MFMAs each) in flight ahead
+      // of the matrix instructions instead of waiting for each read right before its MFMAs.
+      constexpr int kReads = (kKc / 4) * kNt;
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);      // DS reads
+#pragma unroll
+      for (int i = 0; i < kReads - 2; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);    // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+    }
     // the other buffer was last read in the previous stage, which every wave has left
     if (cb + kKc < a.n_chan) deposit(bre2[(it + 1) & 1], bim2[(it + 1) & 1]);
     __syncthreads();
