@@ -9,18 +9,19 @@
 // (N chunks), padded to NT*16.
 //
 // Work decomposition (gfx950, v_mfma_f32_16x16x4_f32, 64-lane waves):
-//  - a workgroup owns 64 DMs (4 waves x 16) and FB = 16 consecutive bins, all chunks;
-//  - channels stream through LDS in groups of KC = 8: the group's data for the 16 bins is
-//    read from HBM once (128-byte runs along f) and rearranged into the two B planes
-//    [c][f][column] (cos-part and sin-part operands), double-buffered: the next group is
-//    deposited into the other buffer right after the current one's products are issued, so
-//    one barrier per group suffices;
+//  - a workgroup owns 64 MW DMs (4 waves x 16 MW) and FB consecutive bins (FB = 8 for the
+//    default tile), all chunks;
+//  - channels stream through LDS in groups of KC (8 by default): the group's data for the FB
+//    bins is read from HBM once (FB x 8-byte runs along f) and rearranged into the two B
+//    planes [c][f][column] (cos-part and sin-part operands), double-buffered: the next group
+//    is deposited into the other buffer right after the current one's products are issued,
+//    so one barrier per group suffices;
 //  - per 4-channel step, lane l generates the phasor of (DM l%16, channel l/16) for the
 //    tile's bins: exact 64-bit phase of the first bin (planner table + sincos_turn), then
-//    complex multiplications by the tabulated step phasor.  Its cos feeds the first MFMA set and its sin the second, so
-//    no phasor is computed twice;
-//  - accumulators live in registers: 16 bins x NT tiles x 4 floats per lane;
-//  - the epilogue writes, per lane, 16 consecutive bins of one (DM, chunk) row of the Yr or
+//    complex multiplications by the tabulated step phasor.  Its cos feeds the first MFMA set
+//    and its sin the second, so no phasor is computed twice;
+//  - accumulators live in registers: FB bins x NT tiles x 4 floats per lane and DM sub-tile;
+//  - the epilogue writes, per lane, FB consecutive bins of one (DM, chunk) row of the Yr or
 //    Yi plane (float4 stores).
 // Workgroups are numbered so that the DM tiles of one bin block run back to back on the same
 // XCD (hardware dispatches workgroup i to XCD i mod 8), so the bin block's data is served
