@@ -454,3 +454,90 @@ def test_scaled_two_channel_closed_form():
     np.testing.assert_allclose(got, want, atol=1e-4)
     # the approximation is not trivially exact here: rows move by whole steps within a block
     assert np.abs(dms[-1] * (f_min + 1) / (f_min + 32) - dms[-1]) > step
+
+
+# ----------------------------------------------------------------------------- 8-bit time-major input (Sec. 3)
+#
+# The paper's 8-bit filterbanks are sample-major and need a transpose before the per-channel
+# transforms (Sec. 3).  These pins build such an array from an explicit formula of (t, c) and
+# check every 8-bit path of the oracle against the same formula read channel-major, so that a
+# transposed, offset or mis-strided read of the time-major layout fails.
+
+def _u8_value(t, c):
+    return (37 * t + 11 * c + 5) % 256
+
+
+def _u8_time_major(n_samp, n_chan):
+    x = np.zeros((n_samp, n_chan), dtype=np.uint8)
+    for t in range(n_samp):
+        for c in range(n_chan):
+            x[t, c] = _u8_value(t, c)
+    return x
+
+
+def _f32_channel_major(n_samp, n_chan):
+    x = np.zeros((n_chan, n_samp), dtype=np.float32)
+    for c in range(n_chan):
+        for t in range(n_samp):
+            x[c, t] = float(_u8_value(t, c))
+    return x
+
+
+@pytest.mark.parametrize("t0,L", [(0, 16), (7, 20), (20, 8), (23, 4)])
+def test_u8_reader_against_formula(t0, L):
+    """input_segment on time-major uint8 [n_samp][n_chan]: out[c, j] = x(t0 + j, c), zero past the data."""
+    n_samp, n_chan = 23, 5
+    x = _u8_time_major(n_samp, n_chan)
+    seg = O.input_segment(x, "u8", t0, L)
+    assert seg.shape == (n_chan, L) and seg.dtype == np.float64
+    for c in range(n_chan):
+        for j in range(L):
+            want = float(_u8_value(t0 + j, c)) if t0 + j < n_samp else 0.0
+            assert seg[c, j] == want, (c, j)
+    sub = O.input_segment(x, "u8", t0, L, channels=slice(1, 4))
+    for i, c in enumerate(range(1, 4)):
+        for j in range(L):
+            want = float(_u8_value(t0 + j, c)) if t0 + j < n_samp else 0.0
+            assert sub[i, j] == want
+
+
+@pytest.mark.parametrize("circular", [True, False])
+def test_u8_tdd_against_loops(circular):
+    """Eq. 2 on 8-bit time-major input, written out over (t, c) with the formula's values."""
+    n_samp, n_chan = 29, 3
+    x = _u8_time_major(n_samp, n_chan)
+    d = np.array([[0, 1, 4], [2, 0, 7], [5, 3, 1]])
+    Lc = 32 if circular else None
+    got = O.tdd(x, "u8", d, circular_len=Lc)
+    for m in range(d.shape[0]):
+        for t in range(n_samp):
+            acc = 0.0
+            for c in range(n_chan):
+                s = t + int(d[m, c])
+                if circular:
+                    s %= 32
+                if s < n_samp:
+                    acc += _u8_value(s, c)
+            assert got[m, t] == acc, (m, t)
+
+
+@pytest.mark.parametrize("mode", ["exact", "round"])
+@pytest.mark.parametrize("single,L,n_samp", [(True, 64, 50), (True, 64, 64), (False, 64, 300)])
+def test_u8_fdd_equals_channel_major_float(mode, single, L, n_samp):
+    """FDD of 8-bit time-major input equals FDD of the same values given channel-major as float."""
+    n_chan = 6
+    w = W.tiny_random(3, n_chan=n_chan, n_samp=n_samp, n_dm=4, chunk_len=L, single_chunk=single, dm_max=0.3)
+    xu = _u8_time_major(n_samp, n_chan)
+    xf = _f32_channel_major(n_samp, n_chan)
+    a = O.fdd(xu, "u8", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, L, single_chunk=single, mode=mode)
+    b = O.fdd(xf, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, L, single_chunk=single, mode=mode)
+    assert a.shape == (4, n_samp)
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-9)
+    if mode == "round":
+        d = O.nearest_sample(O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s))
+        np.testing.assert_allclose(a, _brute_tdd(xf.astype(np.float64), d, L if single else None), atol=1e-9)
+    if single:
+        tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
+        pu = O.oracle_fdd_rows(xu, "u8", tau, L, L, 1, True, mode, power=True)
+        pf = O.oracle_fdd_rows(xf, "f32", tau, L, L, 1, True, mode, power=True)
+        np.testing.assert_allclose(pu, pf, rtol=1e-12, atol=1e-6)
