@@ -1,15 +1,17 @@
 """GPU parity of down-sampled output (Sec. 2.2: a shorter inverse transform for DMs whose
 smearing spans several samples) against the FP64 oracle, row by row.
 
-Tolerances as in the full-resolution parity tests: per DM row ||z - z_ref|| / ||z_ref|| <= 1e-5,
-and for 8-bit input also against the mean-removed row norm (2e-4).  The oracle evaluates the
-same definition, the length-L/d real inverse of bins 0 .. L/(2d) scaled by 1/L, in float64.
+Tolerances as in the full-resolution parity tests (1e-5 per row, element by element through
+`parity.check_rows`: row norm, centred norm, per-sample bound, and the raw-region rule for
+8-bit chunks past the end of the data).  The oracle evaluates the same definition, the
+length-L/d real inverse of bins 0 .. L/(2d) scaled by 1/L, in float64.
 """
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from parity import check_rows, raw_start_of
 
 pytestmark = pytest.mark.gpu
 
@@ -17,15 +19,6 @@ torch = pytest.importorskip("torch")
 fdd = pytest.importorskip("paper_2110_03482_amd")
 
 TOL = 1e-5
-CENTRED_TOL = 2e-4
-
-
-def rel(y, ref):
-    return float(np.linalg.norm(y - ref) / max(np.linalg.norm(ref), 1e-300))
-
-
-def rel_centred(y, ref):
-    return float(np.linalg.norm(y - ref) / max(np.linalg.norm(ref - ref.mean()), 1e-300))
 
 
 def make_input(w, seed):
@@ -46,19 +39,11 @@ def run(w, x, mode, precision, factors):
         return rows, p.geometry, p.kernel
 
 
-def check(w, x, mode, rows, g, factors, label):
+def check(w, x, mode, rows, g, factors, label, tol=TOL):
     ref = O.fdd(x, w.input_kind, w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, overlap=int(g.overlap),
                 single_chunk=w.single_chunk, mode=mode, factors=factors)
-    worst = 0.0
-    for j in range(w.n_dm):
-        assert rows[j].shape == ref[j].shape, (label, j)
-        e = rel(rows[j].astype(np.float64), ref[j])
-        worst = max(worst, e)
-        assert e <= TOL, f"{label}: DM {j} (factor {factors[j]}) rel err {e:.3e}"
-        if w.input_kind == "u8":
-            ec = rel_centred(rows[j].astype(np.float64), ref[j])
-            assert ec <= CENTRED_TOL, f"{label}: DM {j} centred rel err {ec:.3e}"
-    print(f"{label}: max rel err {worst:.3e}", flush=True)
+    raw = [raw_start_of(w.input_kind, g, w.n_samp, w.single_chunk, int(factors[j])) for j in range(w.n_dm)]
+    check_rows(list(rows), list(ref), tol, raw_from=raw, label=label)
 
 
 CASES = [
@@ -137,8 +122,6 @@ def test_paper_shaped_downsampled_sampled_rows():
         sample += [int(idx[0]), int(idx[-1])]
     ref = O.fdd(x, "u8", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, overlap=int(g.overlap),
                 mode="exact", rows=sample, factors=factors)
-    for i, j in enumerate(sample):
-        z = flat[off[j]: off[j + 1]].astype(np.float64)
-        e, ec = rel(z, ref[i]), rel_centred(z, ref[i])
-        print(f"DM {j} factor {factors[j]}: rel err {e:.3e}, centred {ec:.3e}", flush=True)
-        assert e <= TOL and ec <= CENTRED_TOL
+    rows = [flat[off[j]: off[j + 1]] for j in sample]
+    raw = [raw_start_of("u8", g, w.n_samp, False, int(factors[j])) for j in sample]
+    check_rows(rows, list(ref), TOL, raw_from=raw, label=f"paper-shaped down-sampled rows {sample}")

@@ -8,6 +8,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from parity import check_power, check_rows, raw_start_of
 
 pytestmark = pytest.mark.gpu
 
@@ -15,12 +16,6 @@ torch = pytest.importorskip("torch")
 fdd = pytest.importorskip("paper_2110_03482_amd")
 
 TOL = 1e-5
-
-
-def rel_err(y, ref):
-    y = np.asarray(y, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    return np.linalg.norm(y - ref, axis=-1) / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
 
 
 def plan_for(w, mode, precision="fp32", power_only=False):
@@ -52,10 +47,9 @@ def test_long_execute(case, mode):
         y = p.execute(torch.from_numpy(np.ascontiguousarray(x)).cuda())
         torch.cuda.synchronize()
         y = y.cpu().numpy()
+        g = p.geometry
     ref = O.fdd(x, kind, w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, L, single_chunk=single, mode=mode)
-    err = rel_err(y, ref)
-    print(f"max rel err {err.max():.3e}")
-    assert err.max() <= TOL
+    check_rows(y, ref, TOL, raw_from=raw_start_of(kind, g, n_samp, single), label=f"long {case} {mode}")
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16_split", "bf16_split"])
@@ -70,9 +64,8 @@ def test_long_power(precision):
             p.execute(torch.from_numpy(x).cuda())
     tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
     ref = O.oracle_fdd_rows(x, "f32", tau, w.chunk_len, w.chunk_len, 1, True, "exact", power=True)
-    err = rel_err(P, ref)
-    print(f"{precision} long power: max rel err {err.max():.3e}")
-    assert err.max() <= {"fp32": 2 * TOL, "fp16_split": 2 * TOL, "bf16_split": 2e-4}[precision]
+    check_power(P, ref, {"fp32": TOL, "fp16_split": TOL, "bf16_split": 1e-4}[precision],
+                label=f"{precision} long power")
 
 
 def test_periodicity_workload_sampled_rows():
@@ -101,9 +94,7 @@ def test_periodicity_workload_sampled_rows():
     tau = O.delays(w.dms[rows], w.freqs, w.ref_freq_mhz, w.tsamp_s)
     ref = O.oracle_fdd_rows(x, "f32", tau, w.chunk_len, w.chunk_len, 1, True, "exact", power=True)
     print(f"oracle harmonic sums: {ref[:, idx].sum(axis=1)}", flush=True)
-    err = rel_err(Ps, ref)
-    print(f"rows {rows}: rel err {err}", flush=True)
     assert finite
-    assert err.max() <= 2 * TOL
+    check_power(Ps, ref, TOL, label=f"periodicity rows {rows}")
     best = int(np.argmax(hs))
     assert abs(w.dms[best] - 57.0) < 1.0

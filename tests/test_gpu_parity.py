@@ -1,22 +1,18 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
 
-Tolerance (FP32 path): per DM row, ||y - y_ref||_2 / ||y_ref||_2 <= 1e-5.
-
-8-bit rows carry the 128 x n_chan zero-point offset, which could hide errors, so they are also
-checked against the mean-removed row norm.  That bound is looser, CENTRED_TOL = 2e-4, for two
-float32 floors: storing values near 128 x n_chan (RMS rounding 2^-6/sqrt(12) against a
-centred RMS of 16 sqrt(n_chan): 8.8e-6 at 1024 channels), and the last, partial chunk, which
-runs past the data.  Its zero point cannot be removed as a pure DC term, so it holds a
-128 -> 0 step.  At small DMs the step's 1/f spectrum adds coherently over the channels
-(~1e9 at bin 1 for 1024 channels), and float32 accumulation of it leaves an error of
-~1e-4 of the centred norm.  Measured: 9.3e-5 at DM 0.49 (paper-shaped workload), ~1e-6
-at large DMs.
+Tolerance (FP32 path): 1e-5, checked per DM row by `parity.check_rows` as a row norm, a
+mean-removed (centred) norm plus the float32 storage floor, and a per-sample bound of ten
+times the allowed RMS error, so that the 128 n_chan zero-point offset of 8-bit rows cannot hide
+a seam or tail defect.  8-bit chunks that run past the end of the data keep their zero point
+(the 128 -> 0 step there is not a pure DC term); their samples are held to the same 1e-5
+relative to their own uncentred norm (derivation in tests/parity.py).
 """
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from parity import check_power, check_rows, raw_start_of
 
 pytestmark = pytest.mark.gpu
 
@@ -24,22 +20,6 @@ torch = pytest.importorskip("torch")
 fdd = pytest.importorskip("paper_2110_03482_amd")
 
 TOL = 1e-5
-CENTRED_TOL = 2e-4
-
-
-def rel_err(y, ref):
-    y = np.asarray(y, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    num = np.linalg.norm(y - ref, axis=-1)
-    return num / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
-
-
-def rel_err_centred(y, ref):
-    y = np.asarray(y, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    num = np.linalg.norm(y - ref, axis=-1)
-    den = np.linalg.norm(ref - ref.mean(axis=-1, keepdims=True), axis=-1)
-    return num / np.maximum(den, 1e-300)
 
 
 def to_dev(x):
@@ -76,9 +56,7 @@ def test_small_matches_oracle(mode):
     print(f"small workload, mode={mode}", flush=True)
     y, kernel, _ = run_gpu(w, x, mode)
     ref = run_oracle(w, x, mode)
-    err = rel_err(y, ref)
-    print(f"kernel={kernel} max rel err {err.max():.3e}")
-    assert err.max() <= TOL
+    check_rows(y, ref, TOL, label=f"small {mode} kernel={kernel}")
     assert int(np.argmax(y[:, 1000])) == 30
 
 
@@ -87,14 +65,14 @@ def test_small_round_equals_circular_tdd():
     y, _, _ = run_gpu(w, x, "round")
     d = O.nearest_sample(O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s))
     ref = O.tdd(x, "f32", d, circular_len=w.chunk_len)
-    assert rel_err(y, ref).max() <= TOL
+    check_rows(y, ref, TOL, label="small round vs circular TDD")
 
 
 def test_dm_zero_row_is_channel_sum():
     w, x = small_input(2)
     y, _, _ = run_gpu(w, x, "exact")
     ref = x.astype(np.float64).sum(axis=0)
-    assert rel_err(y[0], ref) <= TOL
+    check_rows(y[:1], ref[None], TOL, label="DM 0 vs channel sum")
 
 
 @pytest.mark.parametrize("n_dm", [256, 1024])
@@ -104,7 +82,7 @@ def test_precision_sweep_workload_fp32(n_dm):
     y, _, _ = run_gpu(w, x, "exact")
     rows = list(range(0, n_dm, max(1, n_dm // 64)))
     ref = run_oracle(w, x, "exact", rows=rows)
-    assert rel_err(y[rows], ref).max() <= TOL
+    check_rows(y[rows], ref, TOL, label=f"precision sweep workload fp32 n_dm={n_dm}")
 
 
 # ----------------------------------------------------------------------------- chunked shapes
@@ -133,14 +111,11 @@ def test_chunked_matches_oracle(case, mode):
     print(f"chunked case {case} mode={mode}", flush=True)
     y, kernel, g = run_gpu(w, x, mode)
     ref = run_oracle(w, x, mode)
-    err = rel_err(y, ref)
-    print(f"kernel={kernel} chunks={g.n_chunks} max rel err {err.max():.3e}")
-    assert err.max() <= TOL
-    if kind == "u8":
-        assert rel_err_centred(y, ref).max() <= CENTRED_TOL
+    raw = raw_start_of(kind, g, n_samp, False)
+    check_rows(y, ref, TOL, raw_from=raw, label=f"kernel={kernel} chunks={g.n_chunks}")
     if mode == "round":
         d = O.nearest_sample(O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s))
-        assert rel_err(y, O.tdd(x, kind, d)).max() <= TOL
+        check_rows(y, O.tdd(x, kind, d), TOL, raw_from=raw, label="  vs zero-extended TDD")
 
 
 def test_single_chunk_shorter_than_transform():
@@ -148,14 +123,14 @@ def test_single_chunk_shorter_than_transform():
     x = W.gaussian_f32(w.n_chan, w.n_samp, 3)
     for mode in ("exact", "round"):
         y, _, _ = run_gpu(w, x, mode)
-        assert rel_err(y, run_oracle(w, x, mode)).max() <= TOL
+        check_rows(y, run_oracle(w, x, mode), TOL, label=f"single chunk shorter than L, {mode}")
 
 
 def test_single_channel_single_dm():
     w = W.tiny_random(4, 1, 4096, 1, 4096, single_chunk=True)
     x = W.gaussian_f32(1, 4096, 4)
     y, _, _ = run_gpu(w, x, "exact")
-    assert rel_err(y, run_oracle(w, x, "exact")).max() <= TOL
+    check_rows(y, run_oracle(w, x, "exact"), TOL, label="one channel, one DM")
 
 
 # ----------------------------------------------------------------------------- power spectra
@@ -167,7 +142,7 @@ def test_power_spectrum_small(mode):
     tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
     ref = O.oracle_fdd_rows(x, "f32", tau, w.chunk_len, w.chunk_len, 1, True, mode, power=True)
     # power is quadratic: its relative error is twice that of the amplitudes
-    assert rel_err(P, ref).max() <= 2 * TOL
+    check_power(P, ref, TOL, label=f"power small {mode}")
 
 
 def test_power_spectrum_u8_full_transform():
@@ -176,7 +151,7 @@ def test_power_spectrum_u8_full_transform():
     P, _, _ = run_gpu(w, x, "exact", power=True)
     tau = O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s)
     ref = O.oracle_fdd_rows(x, "u8", tau, w.chunk_len, w.chunk_len, 1, True, "exact", power=True)
-    assert rel_err(P[:, 1:], ref[:, 1:]).max() <= 2 * TOL
+    check_power(P, ref, TOL, skip_dc=True, label="power 8-bit full transform")
     np.testing.assert_allclose(P[:, 0], ref[:, 0], rtol=2e-6)
 
 
@@ -207,12 +182,10 @@ def test_paper_shaped_sampled_rows(paper_input):
     print("paper-shaped workload, exact mode", flush=True)
     y, kernel, g = run_gpu(w, x, "exact")
     assert kernel == "mfma_f32" and g.n_chunks == 21
-    rows = [0, 921]
+    rows = [0, 1, 921, 1842, 2047]
     ref = run_oracle(w, x, "exact", rows=rows)
-    err = rel_err(y[rows], ref)
-    errc = rel_err_centred(y[rows], ref)
-    print(f"rows {rows}: rel err {err}, centred {errc}")
-    assert err.max() <= TOL and errc.max() <= CENTRED_TOL
+    check_rows(y[rows], ref, TOL, raw_from=raw_start_of("u8", g, w.n_samp, False),
+               label=f"paper-shaped exact rows {rows}")
     # properties over every row: finite, DM 0 is the channel sum, pulses found at their trials
     assert np.isfinite(y).all()
     for trial, t0 in ((205, 1 << 18), (921, 1 << 19), (1842, 3 << 18)):
@@ -222,13 +195,9 @@ def test_paper_shaped_sampled_rows(paper_input):
 
 def test_paper_shaped_round_vs_tdd(paper_input):
     w, x = paper_input
-    y, _, _ = run_gpu(w, x, "round")
-    rows = [1, 1842, 2047]
+    y, _, g = run_gpu(w, x, "round")
+    rows = [0, 1, 921, 1842, 2047]
     d = O.nearest_sample(O.delays(w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s))
     ref = O.tdd(x, "u8", d, rows=rows)
-    err = rel_err(y[rows], ref)
-    print(f"round rows {rows}: rel err {err}")
-    errc = rel_err_centred(y[rows], ref)
-    print(f"round rows {rows}: centred rel err {errc}")
-    assert err.max() <= TOL
-    assert errc.max() <= CENTRED_TOL
+    check_rows(y[rows], ref, TOL, raw_from=raw_start_of("u8", g, w.n_samp, False),
+               label=f"paper-shaped round rows {rows} vs TDD")

@@ -11,6 +11,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from parity import check_power
 
 pytestmark = pytest.mark.gpu
 
@@ -61,9 +62,9 @@ def test_scaled_power_matches_oracle(case):
         P = P.cpu().numpy()
         E = E.cpu().numpy()
     ref_p = O.fdd_power_scaled(x, kind, dms, freqs, ref, 64e-6, L, f_min)
-    err = rel(P, ref_p)
-    print(f"{label}: f_min={f_min}, parity max rel err {err.max():.3e}", flush=True)
-    assert np.isfinite(P).all() and err.max() <= TOLS[precision]
+    check_power(P, ref_p, TOLS[precision] / 2, skip_dc=kind == "u8", label=f"{label}: f_min={f_min}, parity")
+    if kind == "u8":
+        np.testing.assert_allclose(P[:, 0], ref_p[:, 0], rtol=2e-5)
     assert np.array_equal(P[:, :f_min], E[:, :f_min])            # low bins: the exact kernels
     if f_min < L // 2:
         approx = rel(P[:, f_min:], E[:, f_min:])
@@ -120,6 +121,4 @@ def test_periodicity_workload_scaled_sampled():
     assert int(np.argmax(hs)) == 467 and int(np.argmax(es)) == 467
     ref = O.fdd_power_scaled(x, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, f_min,
                              rows=rows, bins=bins)
-    err = rel(Ps, ref)
-    print(f"rows {rows}: parity rel err {err}", flush=True)
-    assert err.max() <= TOL
+    check_power(Ps, ref, TOL / 2, label=f"periodicity scaled rows {rows}, parity")

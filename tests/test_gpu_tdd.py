@@ -15,17 +15,12 @@ import pytest
 
 import oracle as O
 import workloads as W
+from parity import check_rows, raw_start
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 fdd = pytest.importorskip("paper_2110_03482_amd")
-
-
-def rel_err(y, ref):
-    y = np.asarray(y, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    return np.linalg.norm(y - ref, axis=-1) / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
 
 
 def plan_of(w, mode="round", power_only=False):
@@ -66,9 +61,7 @@ def test_tdd_matches_oracle(case):
     if kind == "u8":
         assert np.array_equal(y.astype(np.float64), ref), f"max abs diff {np.abs(y - ref).max()}"
     else:
-        err = rel_err(y, ref)
-        print(f"max rel err {err.max():.3e}")
-        assert err.max() <= 1e-6
+        check_rows(y, ref, 1e-6, label=f"tdd {case}")
 
 
 @pytest.mark.parametrize("kind", ["u8", "f32"])
@@ -80,9 +73,8 @@ def test_tdd_equals_fdd_round(kind):
         xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
         yt = p.tdd(xd).cpu().numpy()
         yf = p.execute(xd).cpu().numpy()
-    err = rel_err(yf, yt)
-    print(f"{kind}: FDD (round) vs TDD max rel diff {err.max():.3e}")
-    assert err.max() <= 1e-5
+    raw = raw_start(kind, w.n_samp, w.chunk_len, int(p.geometry.stride), int(p.geometry.n_chunks), False)
+    check_rows(yf, yt, 1e-5, raw_from=raw, label=f"{kind}: FDD (round) vs TDD")
 
 
 def test_tdd_paper_shaped_sampled_rows():
