@@ -126,20 +126,25 @@ typedef struct {
 typedef struct fdd_plan_s* fdd_plan_t;
 
 /* Build a plan: validate the descriptor, copy the host arrays, compute the per-channel delay
- * per unit DM in float64 and the chunk geometry.  Without FDD_PLAN_EXTERNAL_WORKSPACE or
- * FDD_PLAN_DRY_RUN it allocates its workspace on the current device.
+ * per unit DM in float64 (Eq. 1: kappa_c = k_DM (nu_c^-2 - nu_ref^-2) / t_samp, tau = DM kappa_c)
+ * and the chunk geometry of the Sec. 2.2 discard rule (every transformed series loses its last
+ * ceil(max tau) samples to the cyclic wrap, so chunks advance by S = L - D with D >= ceil(max tau),
+ * N_chunk = ceil(n_samp / S)).  Also tabulates, per (channel, DM), the exact 64-bit phase
+ * increment frac(tau / L) 2^64 of Eq. 4 and picks the phasor-sum kernel.  Without
+ * FDD_PLAN_EXTERNAL_WORKSPACE or FDD_PLAN_DRY_RUN it allocates its workspace on the current device.
  * Errors: FDD_E_INVALID, FDD_E_OVERLAP, FDD_E_UNSUPPORTED, FDD_E_NOMEM, FDD_E_DEVICE. */
 fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out);
 
-/* Geometry and workspace size of a plan (host only). */
+/* Geometry (Sec. 2.2: L, S, D, N_chunk, bins L/2 + 1) and workspace size of a plan (host only). */
 fdd_status fdd_plan_info(fdd_plan_t plan, fdd_plan_geometry* out);
 
-/* Attach caller-owned device memory of at least workspace_bytes (256-byte aligned) as the
- * plan's workspace.  Synchronously uploads the plan's small tables into it.  The caller keeps
+/* Infrastructure (no passage of the paper): attach caller-owned device memory of at least
+ * workspace_bytes (256-byte aligned) as the plan's workspace.  Synchronously uploads the plan's small tables into it.  The caller keeps
  * ownership and must keep it alive while the plan is used. */
 fdd_status fdd_set_workspace(fdd_plan_t plan, void* d_workspace, size_t bytes);
 
-/* Dedisperse: d_in is described by the plan's input kind; d_out is float32 [n_dm][n_samp]
+/* Dedisperse (Sec. 2.2, Eqs. 3, 4, 7, 6 and the discard rule; Sec. 3 for the 8-bit transpose and
+ * unpack): d_in is described by the plan's input kind; d_out is float32 [n_dm][n_samp]
  * (DM-major, Sec. 3), or with down-sampling the DM rows one after another, row dm holding
  * ceil(n_samp / d_dm) samples (offsets from fdd_plan_output_offsets).  Enqueued on `stream`;
  * does not synchronise.
@@ -147,7 +152,7 @@ fdd_status fdd_set_workspace(fdd_plan_t plan, void* d_workspace, size_t bytes);
  * FDD_E_WORKSPACE, FDD_E_DEVICE. */
 fdd_status fdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
-/* Start of every output row of fdd_execute, in float32 samples from d_out: offsets[dm] for
+/* Infrastructure: start of every output row of fdd_execute, in float32 samples from d_out: offsets[dm] for
  * dm = 0 .. n_dm, offsets[n_dm] = out_samples (host array of n_dm + 1, written by the call). */
 fdd_status fdd_plan_output_offsets(fdd_plan_t plan, int64_t* offsets);
 
@@ -181,10 +186,11 @@ fdd_status fdd_power_spectrum_scaled(fdd_plan_t plan, const void* d_in, float* d
  * of 8 consecutive DMs differ by more than 4088 samples in some channel. */
 fdd_status fdd_tdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
-/* Release a plan and the workspace it allocated itself (never a caller-owned one). */
+/* Infrastructure: release a plan and the workspace it allocated itself (never a caller-owned one). */
 fdd_status fdd_destroy(fdd_plan_t plan);
 
-/* Stage timing.  fdd_profile_enable(plan, depth) with depth >= 1 makes fdd_execute /
+/* Infrastructure, stage timing (the stage split of the runtime breakdown in Sec. 4.1).
+ * fdd_profile_enable(plan, depth) with depth >= 1 makes fdd_execute /
  * fdd_power_spectrum record HIP events on their stream around each stage, for the first
  * `depth` calls after enabling or after the last read (depth 0 disables).  fdd_profile_read waits for the recorded events and
  * returns the mean milliseconds per call for [0] transpose/unpack, [1] forward FFT,
@@ -244,15 +250,15 @@ fdd_status fdd_batch_create(int32_t n_plans, const fdd_plan_t* plans, const fdd_
  * Errors: FDD_E_INVALID, FDD_E_DEVICE. */
 fdd_status fdd_batch_execute(fdd_batch_t batch, const void* const* d_in, float* const* d_out, void* stream);
 
-/* Sizes: memory waves, scratch bytes, table bytes (any output may be NULL). */
+/* Infrastructure: sizes of a batch -- memory waves, scratch bytes, table bytes (any output may be NULL). */
 fdd_status fdd_batch_info(fdd_batch_t batch, int32_t* n_waves, size_t* scratch_bytes, size_t* table_bytes);
 
-/* JSON description of the waves, shape classes, tuning candidates (with measured ms) and the
+/* Infrastructure: JSON description of the waves, shape classes, tuning candidates (with measured ms) and the
  * chosen kernels, written NUL-terminated into buf[len]; *needed (may be NULL) receives the
  * size required.  FDD_E_INVALID if len is too small. */
 fdd_status fdd_batch_describe(fdd_batch_t batch, char* buf, size_t len, size_t* needed);
 
-/* Release the batch (not its plans). */
+/* Infrastructure: release the batch (not its plans). */
 fdd_status fdd_batch_destroy(fdd_batch_t batch);
 
 /* Host helpers. */
@@ -267,14 +273,15 @@ fdd_status fdd_dispersion_delays(int32_t n_chan, const double* chan_freq_mhz, do
  * smearing, at least 1 and at most max_factor (a power of two >= 1).  Host only. */
 fdd_status fdd_smearing_factors(int32_t n_chan, const double* chan_freq_mhz, double tsamp_s, int32_t n_dm,
                                 const double* dm, int32_t max_factor, int32_t* out);
-/* The plan's float64 delay table tau[n_dm][n_chan] (host copy). */
+/* The plan's float64 delay table tau[n_dm][n_chan] of Eq. 1 (host copy). */
 fdd_status fdd_plan_delays(fdd_plan_t plan, double* tau_out);
-/* Name of the phasor-sum kernel family a plan selected ("valu", "mfma_f32", ...). */
+/* Infrastructure: name of the phasor-sum kernel family a plan selected ("valu", "mfma_f32", ...). */
 const char* fdd_plan_kernel(fdd_plan_t plan);
 
+/* Infrastructure: text of a status code, and of the calling thread's most recent failure. */
 const char* fdd_status_string(fdd_status s);
 const char* fdd_last_error(void);
-/* Library version string. */
+/* Infrastructure: library version string. */
 const char* fdd_version(void);
 
 #ifdef __cplusplus

@@ -48,22 +48,35 @@ def test_split_small(precision, mode):
     assert int(np.argmax(y[:, 1000])) == 30
 
 
+_SWEEP_REF = {}
+
+
+def sweep_reference(w, x):
+    """Oracle rows of the sweep workload (every trial up to 2048 trials, then every
+    n_dm/2048-th), computed once per DM count."""
+    if w.n_dm not in _SWEEP_REF:
+        _SWEEP_REF.clear()
+        rows = list(range(0, w.n_dm, max(1, w.n_dm // 2048)))
+        _SWEEP_REF[w.n_dm] = rows, O.fdd(x, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len,
+                                         single_chunk=True, mode="exact", rows=rows)
+    return _SWEEP_REF[w.n_dm]
+
+
 @pytest.mark.parametrize("precision", ["fp16_split", "bf16_split"])
 @pytest.mark.parametrize("n_dm", [256, 512, 1024, 2048, 4096, 8192])
 def test_precision_sweep(precision, n_dm):
-    """The small band with n_dm trials DM_j = j 64 / n_dm: error per DM count (sampled rows)."""
+    """The small band with n_dm trials DM_j = j 64 / n_dm: error per DM count."""
     w = W.precision_sweep(n_dm)
     x = W.gaussian_f32(w.n_chan, w.n_samp, 0)
     offs = O.nearest_sample(O.delays([30.0], w.freqs, w.ref_freq_mhz, w.tsamp_s))[0]
     W.inject_pulse_f32(x, offs, 1000, 5.0, circular=True)
-    y, _ = run_gpu(w, x, "exact", precision)
+    y, kernel = run_gpu(w, x, "exact", precision)
     y32, _ = run_gpu(w, x, "exact", "fp32")
-    rows = list(range(0, n_dm, max(1, n_dm // 48)))
-    ref = O.fdd(x, "f32", w.dms, w.freqs, w.ref_freq_mhz, w.tsamp_s, w.chunk_len, single_chunk=True, mode="exact",
-                rows=rows)
+    rows, ref = sweep_reference(w, x)
     s32 = check_rows(y32[rows], ref, 1e-5)
     st = check_rows(y[rows], ref, BOUND[precision])
-    print(f"sweep {precision} n_dm={n_dm}: {st.line()} (fp32 path: rel {s32.rel:.3e}, max abs {s32.max_abs:.3e})")
+    print(f"sweep {precision} n_dm={n_dm} kernel={kernel}: {st.line()} "
+          f"(fp32 path: rel {s32.rel:.3e}, centred {s32.centred:.3e}, max abs {s32.max_abs:.3e})")
     # fine grids resolve DM 30 only to within the delay smearing of a few trials
     assert abs(w.dms[int(np.argmax(y[:, 1000]))] - 30.0) <= 0.25
 
