@@ -277,6 +277,12 @@ fdd_status fdd_smearing_factors(int32_t n_chan, const double* chan_freq_mhz, dou
 fdd_status fdd_plan_delays(fdd_plan_t plan, double* tau_out);
 /* Infrastructure: name of the phasor-sum kernel family a plan selected ("valu", "mfma_f32", ...). */
 const char* fdd_plan_kernel(fdd_plan_t plan);
+/* Infrastructure: the DM factorisation a plan uses for a uniform grid with exact delays (Eq. 1 is
+ * linear in DM, so trial a*fine + b has the delay of coarse trial a plus that of fine offset b
+ * and the phasor of Eq. 4 factorises): fine trials per coarse row, coarse rows, and the number
+ * of 32-column matrix-core tiles per column group of the chunked kernels (0 for the others).
+ * All three are 0 for a plan that is not factorised.  Any output pointer may be NULL. */
+fdd_status fdd_plan_factors(fdd_plan_t plan, int32_t* fine, int32_t* coarse, int32_t* col_tiles);
 
 /* Infrastructure: text of a status code, and of the calling thread's most recent failure. */
 const char* fdd_status_string(fdd_status s);

@@ -22,7 +22,7 @@ __all__ = [
     "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
     "fdd_power_spectrum", "fdd_power_spectrum_scaled", "fdd_tdd_execute", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
     "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_output_offsets", "fdd_smearing_factors",
-    "fdd_plan_kernel", "fdd_status_string",
+    "fdd_plan_kernel", "fdd_plan_factors", "fdd_status_string",
     "fdd_last_error", "fdd_version", "Plan", "FDD_BATCH_NO_GRAPH", "FDD_BATCH_NO_AUTOTUNE", "FDD_BATCH_SHARE_PHASORS", "BatchDesc",
     "fdd_batch_create", "fdd_batch_execute", "fdd_batch_info", "fdd_batch_describe", "fdd_batch_destroy", "Batch",
 ]
@@ -116,6 +116,8 @@ _SIGNATURES = {
                                             ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
     "fdd_plan_kernel": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "fdd_plan_factors": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "fdd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "fdd_last_error": (ctypes.c_char_p, []),
     "fdd_version": (ctypes.c_char_p, []),
@@ -262,6 +264,13 @@ def fdd_plan_kernel(plan) -> str:
     return library().fdd_plan_kernel(plan).decode()
 
 
+def fdd_plan_factors(plan) -> tuple:
+    """(fine, coarse, col_tiles) of the plan's DM factorisation; zeros if it is not factorised."""
+    v = [ctypes.c_int32() for _ in range(3)]
+    _check(library().fdd_plan_factors(plan, *[ctypes.byref(x) for x in v]), "fdd_plan_factors")
+    return tuple(int(x.value) for x in v)
+
+
 def fdd_batch_create(plans: Sequence, desc: BatchDesc) -> ctypes.c_void_p:
     arr = (ctypes.c_void_p * len(plans))(*[ctypes.c_void_p(p) if isinstance(p, int) else p for p in plans])
     out = ctypes.c_void_p()
@@ -343,6 +352,7 @@ class Plan:
         self.geometry = fdd_plan_info(self._handle)
         self.downsampled = int(self.geometry.out_samples) != self.n_dm * self.n_samp
         self.kernel = fdd_plan_kernel(self._handle)
+        self.factors = fdd_plan_factors(self._handle)
         self.workspace = None
         self.device = None
         if not dry_run:

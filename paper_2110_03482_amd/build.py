@@ -23,7 +23,7 @@ LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libfdd.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["fft_kernels.hip", "phasor_valu.hip", "phasor_mfma_f32.hip", "phasor_split.hip", "phasor_fac.hip", "phasor_scaled.hip", "tdd.hip"]
+HIP_SOURCES = ["fft_kernels.hip", "phasor_valu.hip", "phasor_mfma_f32.hip", "phasor_split.hip", "phasor_fac.hip", "phasor_facw.hip", "phasor_scaled.hip", "tdd.hip"]
 CPP_SOURCES = ["plan.cpp", "execute.cpp", "batch.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", f"-I{os.path.join(ROOT, 'include')}",

@@ -551,7 +551,8 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
       sk.coarse = (p->desc.n_dm + fine - 1) / fine;
     }
     // the kernel fdd_execute would pick: its own choice for a lone beam, the same rule for a stack
-    const bool fac_default = sk.beams.size() == 1 ? p->fac_fine > 0 : (sk.fine > 0 && sk.n_chunks <= 2);
+    const bool fac_default =
+        sk.beams.size() == 1 ? p->fac_fine > 0 && p->facw_nt == 0 : (sk.fine > 0 && sk.n_chunks <= 2);
     Class c = make_class(p, sk.n_chunks, sk.fine > 0, fac_default);
     auto it = class_of.find(c.key);
     if (it == class_of.end()) {

@@ -86,6 +86,7 @@ PhasorArgs segment_args(fdd_plan_t p, const PhasorArgs& all, const Segment& sg, 
   } else {
     a.Yr = all.Yr + rows;
     a.Yi = all.Yi + rows;
+    if (all.Yc != nullptr) a.Yc = all.Yc + rows;
     a.n_bins = (int)(p->L / sg.factor / 2 + 1);
   }
   return a;
@@ -120,11 +121,13 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   PhasorArgs all = phasor_args(p);
   all.Yr = (float*)(p->d_ws + p->ws.Yr);
   all.Yi = (float*)(p->d_ws + p->ws.Yi);
+  if (p->facw_nt > 0) all.Yc = (float2*)(p->d_ws + p->ws.Yr);   // both planes' memory, interleaved
   hipError_t e = presplit(p, st);
   if (e != hipSuccess) return hip_fail(e, "split launch");
   for (const Segment& sg : p->segs) {
     const PhasorArgs a = segment_args(p, all, sg, false);
-    if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
+    if (p->facw_nt > 0) e = launch_phasor_facw(a, p->desc.precision, p->facw_nt, st);
+    else if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
     else if (p->kernel == "mfma_f32") e = launch_phasor_mfma_f32(a, st);
     else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
     else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
@@ -139,6 +142,7 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
     FftArgs f;
     f.Yr = a.Yr;
     f.Yi = a.Yi;
+    f.Yc = a.Yc;
     f.out = out + sg.out_off;
     f.twL = (const float2*)(p->d_ws + (sg.factor == 1 ? p->ws.tw : sg.tw));
     f.n_samp = sg.n_out;

@@ -17,6 +17,8 @@ struct FftArgs {
   float2* X = nullptr;              // forward output
   const float* Yr = nullptr;        // inverse input planes
   const float* Yi = nullptr;
+  const float2* Yc = nullptr;       // inverse input as interleaved complex [row][pitch] (instead of
+                                    // the planes), written by the DM-factorised chunked kernels
   float* out = nullptr;             // inverse output [n_rows][n_samp]
   const float2* twL = nullptr;
   int64_t n_samp = 0;
@@ -58,6 +60,7 @@ struct PhasorArgs {
   float* Yr = nullptr;              // [n_dm][n_chunks][pitch] (null for power spectra)
   float* Yi = nullptr;
   float* P = nullptr;               // [n_dm][n_pow_bins] power spectra, or null
+  float2* Yc = nullptr;             // [n_dm][n_chunks][pitch] interleaved complex (chunked DM-factorised kernels)
   const uint4* ptab = nullptr;      // [n_chan][n_dm] {inc.lo, inc.hi, step cos, step sin}
   const unsigned int* l1max = nullptr; // [n_chunks] max over channels of the series L1 norm (float bits)
   int n_dm = 0;
@@ -235,6 +238,18 @@ int phasor_fac_fine(int n_chunks);
 hipError_t launch_phasor_fac(const PhasorArgs& a, int precision, hipStream_t st);
 int64_t phasor_fac_tiles(PhasorArgs* a, int precision);
 hipError_t launch_phasor_fac_grouped(int precision, bool persist, const Group<PhasorArgs>& g, hipStream_t st);
+// DM-factorised kernels for overlap-save plans: fine DMs B (8 or 16), coarse rows, and the
+// number NT of 32-column tiles per column group (kFacwNtMin..kFacwNtMax) with the least
+// estimated work for n_dm trials and n_chunks chunks; eff = useful share of the padded tiles.
+// The launch writes interleaved complex Y (a.Yc).
+struct FacwChoice {
+  int fine = 0, coarse = 0, nt = 0;
+  double eff = 0.0;
+};
+constexpr int kFacwNtMin = 4;
+constexpr int kFacwNtMax = 7;
+FacwChoice facw_choose(int n_dm, int n_chunks);
+hipError_t launch_phasor_facw(const PhasorArgs& a, int precision, int nt, hipStream_t st);
 // Spin-frequency-scaled DMs: the per-block matrix products and the resampling in DM.
 // precision FDD_FP32: plain X; split precisions: X split in place by launch_split_x, and the
 // per-chunk L1 maxima for the scale.
@@ -301,6 +316,7 @@ struct fdd_plan_s {
   int tile_variant = 0;                 // FDD_TILE_VARIANT override
   // DM factorisation (uniform DM grid, exact delays): trial j = a * fac_fine + b
   int fac_fine = 0, fac_coarse = 0;     // 0: not factorised
+  int facw_nt = 0;                      // > 0: the chunked factorised kernels with this many column tiles
   int tdd_span = 0;                     // largest delay spread over 8 consecutive DMs (time-domain kernel)
   int tdd_span64 = 0;                   // ... over tdd_tile64() consecutive DMs
   double fac_dm0 = 0.0, fac_step = 0.0;

@@ -178,7 +178,9 @@ __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_r2c_grouped(Group<FftArg
 
 // ----------------------------------------------------------------------------- inverse
 
-template <int LOGN, int LOGE>
+// INTER: Y is read as interleaved complex a.Yc (chunked DM-factorised phasor sums), else as the
+// planes a.Yr, a.Yi.
+template <int LOGN, int LOGE, bool INTER>
 __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const int dm) {
   using F = BlockFft<LOGN, LOGE, true>;
   constexpr int N = F::N, E = F::E, T = F::T;
@@ -196,14 +198,23 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   const int64_t row = ((int64_t)dm * row_chunks + k) * pitch;
   const float* yr = Yr + row;
   const float* yi = Yi + row;
+  const float2* yc = a.Yc + row;
   const float scale = a.inv_n > 0.0f ? a.inv_n : 1.0f / (float)N;
   float2 v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int f = t + T * q;
     const int fm = N - f;                                      // in 1 .. N
-    const float2 yf = make_float2(yr[f], f == 0 ? 0.0f : yi[f]);
-    const float2 ym = make_float2(yr[fm], fm == N ? 0.0f : -yi[fm]);   // conj Y[N - f]
+    float2 yf, ym;
+    if constexpr (INTER) {
+      yf = yc[f];
+      ym = yc[fm];
+      yf.y = f == 0 ? 0.0f : yf.y;
+      ym.y = fm == N ? 0.0f : -ym.y;                           // conj Y[N - f]
+    } else {
+      yf = make_float2(yr[f], f == 0 ? 0.0f : yi[f]);
+      ym = make_float2(yr[fm], fm == N ? 0.0f : -yi[fm]);      // conj Y[N - f]
+    }
     const float2 a = make_float2(0.5f * (yf.x + ym.x), 0.5f * (yf.y + ym.y));
     const float2 d = make_float2(0.5f * (yf.x - ym.x), 0.5f * (yf.y - ym.y));
     const float2 w = twL[f];                                   // exp(-2 pi i f / L); use conj
@@ -225,9 +236,9 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   }
 }
 
-template <int LOGN, int LOGE>
+template <int LOGN, int LOGE, bool INTER>
 __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_c2r(FftArgs a) {
-  c2r_body<LOGN, LOGE>(a, blockIdx.x, blockIdx.y);
+  c2r_body<LOGN, LOGE, INTER>(a, blockIdx.x, blockIdx.y);
 }
 
 template <int LOGN, int LOGE>
@@ -238,7 +249,7 @@ __global__ __launch_bounds__(1 << (LOGN - LOGE)) void k_c2r_grouped(Group<FftArg
   const FftArgs a = g.beams[b];
   const int lid = bid - g.prefix[b];
   if (lid >= a.n_chunks * a.n_rows) return;
-  c2r_body<LOGN, LOGE>(a, lid % a.n_chunks, lid / a.n_chunks);
+  c2r_body<LOGN, LOGE, false>(a, lid % a.n_chunks, lid / a.n_chunks);
 }
 
 // ----------------------------------------------------------------------------- long transforms
@@ -564,7 +575,10 @@ template <int LOGN>
 hipError_t launch_c2r_n(const FftArgs& a, hipStream_t st) {
   constexpr int LOGE = fft_loge_inv<LOGN>();
   dim3 grid((unsigned)a.n_chunks, (unsigned)a.n_rows);
-  hipLaunchKernelGGL((k_c2r<LOGN, LOGE>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a);
+  if (a.Yc != nullptr)
+    hipLaunchKernelGGL((k_c2r<LOGN, LOGE, true>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_c2r<LOGN, LOGE, false>), grid, dim3(1 << (LOGN - LOGE)), 0, st, a);
   return hipGetLastError();
 }
 }  // namespace

@@ -469,13 +469,10 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     const int v = std::atoi(tv);
     if (v >= 0 && v <= 4) p->tile_variant = v;
   }
-  if (d.precision == FDD_FP16_SPLIT || d.precision == FDD_BF16_SPLIT) {
-    if (!phasor_split_supported((int)p->n_chunks)) {
-      delete p;
-      return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums support 1 to 24 chunks");
-    }
-    p->kernel = d.precision == FDD_FP16_SPLIT ? "mfma_f16_split" : "mfma_bf16_split";
-  }
+  // the direct split kernels take 1 to 24 chunks; other counts need a factorised kernel below
+  if (d.precision == FDD_FP16_SPLIT || d.precision == FDD_BF16_SPLIT)
+    p->kernel = !phasor_split_supported((int)p->n_chunks) ? ""
+                : d.precision == FDD_FP16_SPLIT ? "mfma_f16_split" : "mfma_bf16_split";
   // DM factorisation: exact delays on a uniform DM grid, few chunks (where the direct kernels
   // leave most matrix-core columns empty).  FDD_FACTOR=0 disables it, FDD_FACTOR=all extends
   // it to every chunk count the factorised kernels take.
@@ -493,6 +490,35 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
       p->fac_step = step;
       p->kernel = d.precision == FDD_FP32 ? "fac_f32" : d.precision == FDD_FP16_SPLIT ? "fac_f16_split" : "fac_bf16_split";
     }
+    // Overlap-save plans: the chunked factorised kernels, in which every coarse phasor serves
+    // 2 B N matrix-core columns instead of the direct kernels' 2 N.  They need the inverse's
+    // interleaved Y (so not for power-only plans) and a one-workgroup inverse transform.
+    // FDD_FACTOR=direct keeps the direct kernels.  In FP32 the direct matrix-core kernel is
+    // the faster one on the paper-shaped workload (its phasor generation is a small share of
+    // the FP32 products), so FP32 plans take the chunked factorised kernel only with
+    // FDD_FACTOR=wide.
+    const bool direct = fe != nullptr && std::strcmp(fe, "direct") == 0;
+    const bool wide = fe != nullptr && std::strcmp(fe, "wide") == 0;
+    if (!off && !direct && (d.precision != FDD_FP32 || wide) && p->fac_fine == 0 && d.delay_mode == FDD_DELAY_EXACT &&
+        !d.single_chunk && max_ds == 1 &&
+        !(d.flags & FDD_PLAN_POWER_ONLY) && p->log_len - 1 <= kMaxBlockLogN && p->n_chunks >= 3 &&
+        uniform_grid(p->dms, &dm0, &step)) {
+      const FacwChoice ch = facw_choose(d.n_dm, (int)p->n_chunks);
+      if (ch.fine > 0 && ch.eff >= 0.7) {
+        p->fac_fine = ch.fine;
+        p->fac_coarse = ch.coarse;
+        p->facw_nt = ch.nt;
+        p->fac_dm0 = dm0;
+        p->fac_step = step;
+        p->kernel = d.precision == FDD_FP32 ? "facw_f32" : d.precision == FDD_FP16_SPLIT ? "facw_f16_split"
+                                                                                          : "facw_bf16_split";
+      }
+    }
+  }
+  if (p->kernel.empty()) {
+    delete p;
+    return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums support 1 to 24 chunks unless the DM grid is "
+                                   "uniform with exact delays (DM-factorised kernels)");
   }
   // spin-frequency-scaled DMs (Eq. 8): first block whose rows stay within the halo
   if (d.flags & FDD_PLAN_SCALED_DM) {
@@ -596,6 +622,14 @@ fdd_status fdd_plan_delays(fdd_plan_t p, double* tau) {
 }
 
 const char* fdd_plan_kernel(fdd_plan_t p) { return p == nullptr ? "" : p->kernel.c_str(); }
+
+fdd_status fdd_plan_factors(fdd_plan_t p, int32_t* fine, int32_t* coarse, int32_t* col_tiles) {
+  if (p == nullptr) return fail(FDD_E_INVALID, "null plan");
+  if (fine != nullptr) *fine = p->fac_fine;
+  if (coarse != nullptr) *coarse = p->fac_coarse;
+  if (col_tiles != nullptr) *col_tiles = p->facw_nt;
+  return FDD_OK;
+}
 
 fdd_status fdd_set_workspace(fdd_plan_t p, void* mem, size_t bytes) {
   if (p == nullptr || mem == nullptr) return fail(FDD_E_INVALID, "null plan or workspace");

@@ -70,8 +70,20 @@ def test_dry_run_geometry_paper_shaped():
     expect = (w.n_chan * n * g.bins_padded * 8 + 2 * w.n_dm * n * g.bins_padded * 4 + w.n_chan * w.n_samp
               + 16 * w.n_chan * w.n_dm)
     assert expect <= g.workspace_bytes < expect + (1 << 24)
-    assert p.kernel == "mfma_f32"
+    assert p.kernel == "mfma_f32" and p.factors == (0, 0, 0)      # FP32: direct kernel by default
     p.close()
+    # uniform grid, exact delays, 21 chunks, split precision: DM-factorised chunked kernels, 16
+    # fine trials per coarse row (128 rows), 7 tiles per column group (3 groups of 112 columns)
+    p = _dry(w, precision="fp16_split")
+    assert p.kernel == "facw_f16_split" and p.factors == (16, 128, 7)
+    p.close()
+    os.environ["FDD_FACTOR"] = "wide"
+    try:
+        p = _dry(w)
+        assert p.kernel == "facw_f32" and p.factors == (16, 128, 7)
+        p.close()
+    finally:
+        del os.environ["FDD_FACTOR"]
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -149,7 +161,44 @@ def test_kernel_selection():
     p = _dry(w2)                                         # random (non-uniform) DMs
     assert p.geometry.n_chunks >= 3 and p.kernel == "mfma_f32"
     w3 = W.paper_shaped_u8()
-    assert _dry(w3).kernel == "mfma_f32"                 # 21 chunks: direct kernel
+    assert _dry(w3).kernel == "mfma_f32"                 # 21 chunks, FP32: direct kernel
+    assert _dry(w3, precision="fp16_split").kernel == "facw_f16_split"   # split: chunked factorised
+    assert _dry(w3, precision="bf16_split").kernel == "facw_bf16_split"
+    assert _dry(w3, precision="fp16_split", mode="round").kernel == "mfma_f16_split"   # rounding does not factorise
+    assert _dry(w3, precision="fp16_split", power_only=True).kernel == "mfma_f16_split"   # needs the Y buffer
+    assert _dry(w3, mode="round").factors == (0, 0, 0)
+    os.environ["FDD_FACTOR"] = "direct"
+    try:
+        assert _dry(w3, precision="fp16_split").kernel == "mfma_f16_split"
+    finally:
+        del os.environ["FDD_FACTOR"]
+
+
+def test_chunked_factorised_selection():
+    """Chunked plans on uniform grids with exact delays take the DM-factorised chunked kernels in
+    split precision, with the column-group width following the chunk count, and at any chunk
+    count (the direct split kernels stop at 24 chunks)."""
+    import dataclasses
+    seen, chunks = set(), []
+    for n_samp in (21900, 15000, 9000, 40000, 90000):
+        w = W.tiny_random(11, 48, n_samp, 2048, 2048, single_chunk=False, input_kind="f32")
+        w = dataclasses.replace(w, dms=np.linspace(0.0, 40.0, 2048))
+        p = _dry(w, precision="fp16_split")
+        assert p.kernel == "facw_f16_split" and p.factors[0] in (8, 16), (n_samp, p.kernel)
+        seen.add(p.factors[2])
+        chunks.append(int(p.geometry.n_chunks))
+        p.close()
+        r = fdd.Plan(w.freqs, w.ref_freq_mhz, w.tsamp_s, w.dms, w.n_samp, w.chunk_len, input="f32",
+                     precision="fp16_split", mode="round", dry_run=True) if n_samp <= 30000 else None
+        if r is not None:
+            assert r.kernel == "mfma_f16_split"
+            r.close()
+    assert len(seen) >= 2 and max(chunks) > 24, (seen, chunks)
+    # more than 24 chunks without a factorisation: rejected
+    w = W.tiny_random(11, 48, 90000, 2048, 2048, single_chunk=False, input_kind="f32")
+    with pytest.raises(fdd.FddError) as e:
+        _dry(w, precision="fp16_split")
+    assert e.value.status == 3
 
 
 def test_batch_rejects_without_device_calls():

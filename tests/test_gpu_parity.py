@@ -7,6 +7,8 @@ a seam or tail defect.  8-bit chunks that run past the end of the data keep thei
 (the 128 -> 0 step there is not a pure DC term); their samples are held to the same 1e-5
 relative to their own uncentred norm (derivation in tests/parity.py).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -176,12 +178,20 @@ def paper_input():
     return w, x
 
 
-def test_paper_shaped_sampled_rows(paper_input):
-    """1024 ch x 2^20 8-bit samples x 2048 DMs, L = 2^16 (21 chunks): rows checked against the oracle."""
+@pytest.mark.parametrize("factor", ["default", "wide"])
+def test_paper_shaped_sampled_rows(paper_input, factor):
+    """1024 ch x 2^20 8-bit samples x 2048 DMs, L = 2^16 (21 chunks): rows checked against the
+    oracle, on the direct FP32 kernel (the default) and on the chunked DM-factorised FP32 kernel
+    (FDD_FACTOR=wide)."""
     w, x = paper_input
-    print("paper-shaped workload, exact mode", flush=True)
-    y, kernel, g = run_gpu(w, x, "exact")
-    assert kernel == "mfma_f32" and g.n_chunks == 21
+    print(f"paper-shaped workload, exact mode, {factor} kernel", flush=True)
+    if factor == "wide":
+        os.environ["FDD_FACTOR"] = "wide"
+    try:
+        y, kernel, g = run_gpu(w, x, "exact")
+    finally:
+        os.environ.pop("FDD_FACTOR", None)
+    assert kernel == ("facw_f32" if factor == "wide" else "mfma_f32") and g.n_chunks == 21
     rows = [0, 1, 921, 1842, 2047]
     ref = run_oracle(w, x, "exact", rows=rows)
     check_rows(y[rows], ref, TOL, raw_from=raw_start_of("u8", g, w.n_samp, False),

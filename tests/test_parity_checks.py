@@ -75,3 +75,18 @@ def test_power_check_catches_a_bad_bin():
     P[1, 77] *= 1.01
     with pytest.raises(AssertionError):
         check_power(P, ref, 1e-5)
+
+
+def test_power_check_scales_with_the_bin():
+    # a bin holding a large coherent power is held to its own size: 2e-7 relative there passes,
+    # while the same absolute error in a typical bin fails
+    rng = np.random.default_rng(4)
+    ref = rng.exponential(1e9, size=(1, 8192))
+    ref[0, 0] = 3.7e14
+    P = ref.copy()
+    P[0, 0] *= 1 + 2e-7
+    check_power(P, ref, 1e-5)
+    P = ref.copy()
+    P[0, 5] += 3.7e14 * 2e-7
+    with pytest.raises(AssertionError):
+        check_power(P, ref, 1e-5)
