@@ -60,6 +60,9 @@ KERNEL_SOURCES = {
     "fac_f32": "paper_2110_03482_amd/csrc/phasor_fac.hip",
     "fac_f16_split": "paper_2110_03482_amd/csrc/phasor_fac.hip",
     "fac_bf16_split": "paper_2110_03482_amd/csrc/phasor_fac.hip",
+    "facw_f32": "paper_2110_03482_amd/csrc/phasor_facw.hip",
+    "facw_f16_split": "paper_2110_03482_amd/csrc/phasor_facw.hip",
+    "facw_bf16_split": "paper_2110_03482_amd/csrc/phasor_facw.hip",
 }
 
 
