@@ -152,6 +152,18 @@ fdd_status fdd_set_workspace(fdd_plan_t plan, void* d_workspace, size_t bytes);
  * FDD_E_WORKSPACE, FDD_E_DEVICE. */
 fdd_status fdd_execute(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
 
+/* For callers that cannot allocate device memory at execution time (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fdd_execute with the plan's
+ * workspace in the library's static device scratch instead of the plan's own memory.  The plan
+ * may be a dry-run plan (FDD_PLAN_DRY_RUN: no device memory at all); its workspace_bytes must be
+ * at most 64 MiB (FDD_E_UNSUPPORTED otherwise).  The call enqueues on `stream` the upload of the
+ * plan's tables (kept on the host since fdd_plan) into the scratch, then the same kernels as
+ * fdd_execute; it calls no hipMalloc or hipFree.  The scratch is one 64 MiB array per device,
+ * held until the process ends and shared by every call on that device: calls that overlap on one
+ * device race with each other, so the caller orders them (one stream, or events).  Output and
+ * errors as fdd_execute (a dry-run plan is accepted). */
+fdd_status fdd_execute_noalloc(fdd_plan_t plan, const void* d_in, float* d_out, void* stream);
+
 /* Infrastructure: start of every output row of fdd_execute, in float32 samples from d_out: offsets[dm] for
  * dm = 0 .. n_dm, offsets[n_dm] = out_samples (host array of n_dm + 1, written by the call). */
 fdd_status fdd_plan_output_offsets(fdd_plan_t plan, int64_t* offsets);

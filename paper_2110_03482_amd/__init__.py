@@ -19,7 +19,7 @@ __all__ = [
     "FDD_OK", "FDD_IN_U8_TIME_MAJOR", "FDD_IN_F32_CHAN_MAJOR", "FDD_FP32", "FDD_FP16_SPLIT",
     "FDD_BF16_SPLIT", "FDD_DELAY_EXACT", "FDD_DELAY_ROUND", "FDD_PLAN_DRY_RUN",
     "FDD_PLAN_EXTERNAL_WORKSPACE", "FDD_PLAN_POWER_ONLY", "FDD_PLAN_SCALED_DM", "FddError", "PlanDesc", "PlanGeometry", "library", "library_path",
-    "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute",
+    "exported_symbols", "fdd_plan", "fdd_plan_info", "fdd_set_workspace", "fdd_execute", "fdd_execute_noalloc",
     "fdd_power_spectrum", "fdd_power_spectrum_scaled", "fdd_tdd_execute", "fdd_destroy", "fdd_profile_enable", "fdd_profile_read",
     "fdd_dispersion_delays", "fdd_plan_delays", "fdd_plan_output_offsets", "fdd_smearing_factors",
     "fdd_plan_kernel", "fdd_plan_factors", "fdd_status_string",
@@ -101,6 +101,7 @@ _SIGNATURES = {
     "fdd_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PlanGeometry)]),
     "fdd_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "fdd_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdd_execute_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_power_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_tdd_execute": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdd_power_spectrum_scaled": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -194,6 +195,11 @@ def fdd_set_workspace(plan, ptr: int, nbytes: int) -> None:
 def fdd_execute(plan, d_in: int, d_out: int, stream: int = 0) -> None:
     _check(library().fdd_execute(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out), ctypes.c_void_p(stream)),
            "fdd_execute")
+
+
+def fdd_execute_noalloc(plan, d_in: int, d_out: int, stream: int = 0) -> None:
+    _check(library().fdd_execute_noalloc(plan, ctypes.c_void_p(d_in), ctypes.c_void_p(d_out), ctypes.c_void_p(stream)),
+           "fdd_execute_noalloc")
 
 
 def fdd_power_spectrum(plan, d_in: int, d_out: int, stream: int = 0) -> None:
@@ -409,6 +415,17 @@ class Plan:
         elif out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous():
             raise ValueError(f"out must be a contiguous float32 tensor of shape {shape}")
         fdd_execute(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
+        return out
+
+    def execute_noalloc(self, x, out, stream=None):
+        """execute() with the workspace in the library's static device scratch (no device
+        allocation by the call; dry-run plans accepted).  out: float32 as execute() returns."""
+        import torch
+        self._check_input(x)
+        shape = (int(self.geometry.out_samples),) if self.downsampled else (self.n_dm, self.n_samp)
+        if out.dtype != torch.float32 or tuple(out.shape) != shape or not out.is_contiguous() or out.device != x.device:
+            raise ValueError(f"out must be a contiguous float32 tensor of shape {shape} on the input's device")
+        fdd_execute_noalloc(self._handle, x.data_ptr(), out.data_ptr(), self._stream(stream))
         return out
 
     def tdd(self, x, out=None, stream=None):

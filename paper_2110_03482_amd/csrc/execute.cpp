@@ -1,10 +1,16 @@
 // Stage sequencing of fdd_execute / fdd_power_spectrum (Algorithm 1 without host copies:
 // inputs and outputs are device resident, so there is nothing to overlap with PCIe).
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "fdd_internal.h"
 
 using namespace fdd;
+
+// The static scratch of fdd_execute_noalloc (see scratch_address below for how host code reaches it).
+static constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
 
 namespace {
 
@@ -99,6 +105,33 @@ hipError_t presplit(fdd_plan_t p, hipStream_t st) {
                         p->desc.n_chan, (int)p->n_chunks, p->pitch, p->kernel == "mfma_bf16_split", st);
 }
 
+// Static scratch of fdd_execute_noalloc: the workspace of plans that execute without any
+// device allocation.  One array per device, shared by every call on that device, for the whole
+// process.  Host code reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is a host-side stand-in, not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+
+// The scratch's device address on the current device, looked up once per device.
+fdd_status scratch_address(uint8_t** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(FDD_E_UNSUPPORTED, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = (uint8_t*)ptr;
+  }
+  *out = g_scratch[dev];
+  return FDD_OK;
+}
+
+fdd_status execute_body(fdd_plan_t p, const void* in, float* out, hipStream_t st);
+
 // Chunks k whose input samples [kS, kS + L) all lie inside the data.
 int full_chunks(fdd_plan_t p) {
   const int64_t n = p->desc.n_samp;
@@ -114,7 +147,36 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   fdd_status s = check_ready(p, in, out);
   if (s != FDD_OK) return s;
   if (p->desc.flags & FDD_PLAN_POWER_ONLY) return fail(FDD_E_UNSUPPORTED, "the plan was made for power spectra only");
+  return execute_body(p, in, out, (hipStream_t)stream);
+}
+
+fdd_status fdd_execute_noalloc(fdd_plan_t p, const void* in, float* out, void* stream) {
+  if (p == nullptr) return fail(FDD_E_INVALID, "null plan");
+  if (in == nullptr || out == nullptr) return fail(FDD_E_INVALID, "null input or output");
+  if (p->desc.flags & FDD_PLAN_POWER_ONLY) return fail(FDD_E_UNSUPPORTED, "the plan was made for power spectra only");
+  if (p->ws.total > kNoallocScratchBytes)
+    return fail(FDD_E_UNSUPPORTED, "the plan's workspace (" + std::to_string(p->ws.total) +
+                                       " bytes) exceeds the static scratch of " + std::to_string(kNoallocScratchBytes) +
+                                       " bytes of fdd_execute_noalloc");
+  uint8_t* ws = nullptr;
+  fdd_status s = scratch_address(&ws);
+  if (s != FDD_OK) return s;
   hipStream_t st = (hipStream_t)stream;
+  hipError_t e = upload_tables_async(p, ws, st);
+  if (e != hipSuccess) return hip_fail(e, "table upload into the static scratch");
+  uint8_t* const own = p->d_ws;
+  p->d_ws = ws;                            // the kernels address the workspace through the plan
+  s = execute_body(p, in, out, st);
+  p->d_ws = own;
+  return s;
+}
+
+}  // extern "C"
+
+namespace {
+
+fdd_status execute_body(fdd_plan_t p, const void* in, float* out, hipStream_t st) {
+  fdd_status s;
   mark(p, 0, st);
   s = forward(p, in, st);
   if (s != FDD_OK) return s;
@@ -165,6 +227,10 @@ fdd_status fdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   mark(p, 4, st);
   return FDD_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 fdd_status fdd_tdd_execute(fdd_plan_t p, const void* in, float* out, void* stream) {
   fdd_status s = check_ready(p, in, out);

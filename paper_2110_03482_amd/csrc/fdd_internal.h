@@ -323,6 +323,8 @@ struct fdd_plan_s {
   // output down-sampling: the factor of every DM and the runs of equal factors (one segment
   // of factor 1 without down-sampling)
   std::vector<int32_t> ds;
+  // the small tables on the host, uploaded into the workspace: (workspace byte offset, bytes)
+  std::vector<std::pair<size_t, std::vector<uint8_t>>> htabs;
   std::vector<fdd::Segment> segs;
   int64_t out_total = 0;
   // spin-frequency-scaled DMs (FDD_PLAN_SCALED_DM)
@@ -347,6 +349,8 @@ void phase_table_rows(const fdd_plan_s* p, int j0, int n, std::vector<uint4>* ou
 // plus fine [n_chan][fine] phase tables of trial a * fine + b.
 bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step);
 void factor_tables(const fdd_plan_s* p, int fine, int coarse, double dm0, double step, std::vector<uint4>* out);
+// Enqueue the copies of the plan's host tables into a workspace at dst (same layout) on st.
+hipError_t upload_tables_async(const fdd_plan_s* p, uint8_t* dst, hipStream_t st);
 void set_error(const std::string& msg);
 fdd_status fail(fdd_status s, const std::string& msg);
 fdd_status hip_fail(hipError_t e, const char* what);

@@ -160,17 +160,23 @@ static void delay_table(const fdd_plan_s* p, std::vector<int>* out) {
     for (size_t m = 0; m < nd; ++m) (*out)[c * nd + m] = (int)std::floor(p->dms[m] * p->kappa[c] + 0.5);
 }
 
-static fdd_status upload_tables(fdd_plan_s* p) {
+// The plan's small tables (twiddles, phase and delay tables, scaled-DM tables), computed once on
+// the host at plan time and kept with the plan: each is (workspace byte offset, bytes).
+static void build_host_tables(fdd_plan_s* p) {
   const WorkspaceLayout& w = p->ws;
+  p->htabs.clear();
+  auto keep = [&](size_t off, const void* src, size_t bytes) {
+    std::vector<uint8_t> b(bytes);
+    std::memcpy(b.data(), src, bytes);
+    p->htabs.emplace_back(off, std::move(b));
+  };
   std::vector<float2> tw;
   twiddle_table(p->L, &tw);
-  hipError_t e = hipMemcpy(p->d_ws + w.tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(twiddles)");
+  keep(w.tw, tw.data(), tw.size() * sizeof(float2));
   for (const Segment& sg : p->segs) {
     if (sg.factor == 1) continue;
     twiddle_table(p->L / sg.factor, &tw);   // several segments may share a factor: same bytes
-    e = hipMemcpy(p->d_ws + sg.tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(short twiddles)");
+    keep(sg.tw, tw.data(), tw.size() * sizeof(float2));
   }
   std::vector<uint4> tab;
   if (p->fac_fine > 0) {
@@ -182,21 +188,32 @@ static fdd_status upload_tables(fdd_plan_s* p) {
       tab.insert(tab.end(), part.begin(), part.end());
     }
   }
-  e = hipMemcpy(p->d_ws + w.ptab, tab.data(), tab.size() * sizeof(uint4), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(phase table)");
+  keep(w.ptab, tab.data(), tab.size() * sizeof(uint4));
   std::vector<int> dt;
   delay_table(p, &dt);
-  e = hipMemcpy(p->d_ws + w.dtab, dt.data(), w.dtab_bytes, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(delay table)");
+  keep(w.dtab, dt.data(), w.dtab_bytes);
   if (p->scaled) {
     std::vector<uint4> ct;
     scaled_table(p, &ct);
-    e = hipMemcpy(p->d_ws + w.ctab, ct.data(), w.ctab_bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(scaled-DM table)");
-    e = hipMemcpy(p->d_ws + w.dmv, p->dms.data(), w.dmv_bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(trial DMs)");
+    keep(w.ctab, ct.data(), w.ctab_bytes);
+    keep(w.dmv, p->dms.data(), w.dmv_bytes);
+  }
+}
+
+static fdd_status upload_tables(fdd_plan_s* p) {
+  for (const auto& t : p->htabs) {
+    const hipError_t e = hipMemcpy(p->d_ws + t.first, t.second.data(), t.second.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
   }
   return FDD_OK;
+}
+
+hipError_t upload_tables_async(const fdd_plan_s* p, uint8_t* dst, hipStream_t st) {
+  for (const auto& t : p->htabs) {
+    const hipError_t e = hipMemcpyAsync(dst + t.first, t.second.data(), t.second.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 static fdd_status layout(fdd_plan_s* p) {
@@ -567,6 +584,7 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     return st;
   }
   p->dry_run = (d.flags & FDD_PLAN_DRY_RUN) != 0;
+  build_host_tables(p);
   if (!p->dry_run && !(d.flags & FDD_PLAN_EXTERNAL_WORKSPACE)) {
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, p->ws.total);
