@@ -18,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_math.h"
 
 namespace fdd {
@@ -121,11 +123,51 @@ struct LdsSize {
   static constexpr int floats = (1 << LOGN) + ((1 << LOGN) >> 5);
 };
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E-1.
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// d * exp(sign * 2 pi i M / D), sign -1 (forward) or +1 (INV), for compile-time M and D; the
+// quarter turns are exact and the rest costs one complex multiplication by constants.
+template <int M, int D, bool INV>
+__device__ __forceinline__ float2 rotate_const(float2 d) {
+  constexpr int m = M % D;
+  if constexpr (m == 0) {
+    return d;
+  } else if constexpr (2 * m == D) {
+    return make_float2(-d.x, -d.y);
+  } else if constexpr (4 * m == D) {
+    return INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+  } else if constexpr (4 * m == 3 * D) {
+    return INV ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+  } else {
+    constexpr double ang = (INV ? 2.0 : -2.0) * kPi * m / D;
+    constexpr float c = (float)cx_cos(ang), s = (float)cx_sin(ang);
+    return make_float2(fmaf(d.x, c, -d.y * s), fmaf(d.x, s, d.y * c));
+  }
+}
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
 template <int LOGN, int LOGE, bool INV, int LOGRMAX = 4>
 struct BlockFft {
   static constexpr int N = 1 << LOGN;
   static constexpr int E = 1 << LOGE;
   static constexpr int T = N / E;
+
+  // Padded LDS index of point i; for T >= 32 the read side of an exchange reduces to
+  // rd0 + q (T + T/32), rd0 = t + t/32.
+  __device__ __forceinline__ static int read_index(int t, int q) {
+    if constexpr (T >= 32) return t + (t >> 5) + q * (T + T / 32);
+    else return lds_pad(t + T * q);
+  }
 
   // One Stockham pass over sub-transform size Ns = 2^LOGNS; recursion runs the rest.
   template <int LOGNS>
@@ -138,43 +180,50 @@ struct BlockFft {
       constexpr int Ns = 1 << LOGNS;
       constexpr bool last = (LOGNS + LOGR == LOGN);
       const int t = threadIdx.x;
-      // butterflies in place: the outputs of butterfly b overwrite its inputs, slot b + r*NB
+      // Pass twiddles.  Butterfly b = 0 .. NB-1 of thread t is j = t + T b, k = j mod Ns, and
+      // scales its input r by w^r, w = exp(-/+ 2 pi i k / (Ns R)).  For Ns <= T every b has
+      // k0 = t mod Ns; for Ns > T, k = t + T b' with b' = b mod (Ns / T), and the extra factor
+      // exp(-/+ 2 pi i r T b' / (Ns R)) is a compile-time constant.  So only the twiddles of k0
+      // are evaluated: the angle r k0 / (Ns R) of a turn is an exact 32-bit fixed-point
+      // fraction; for R > 8 w^r = w^(8u) w^v (r = 8u + v) takes R/8 + 6 evaluations instead of
+      // R - 1, at one extra rounding for some r.
+      float2 tw[R];
+      if constexpr (Ns > 1) {
+        constexpr int SH = 32 - LOGNS - LOGR;
+        constexpr int G = R > 8 ? 8 : R;
+        const uint32_t k0 = (uint32_t)t & (uint32_t)(Ns - 1);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int j = t + T * b;
-        const int k = j & (Ns - 1);
+        for (int vv = 1; vv < G; ++vv) tw[vv] = turn_phasor<INV>((uint32_t)(vv * k0) << SH);
+#pragma unroll
+        for (int u = 1; u < R / G; ++u) {
+          const float2 hi = turn_phasor<INV>((uint32_t)(u * G * k0) << SH);
+          tw[u * G] = hi;
+#pragma unroll
+          for (int vv = 1; vv < G; ++vv) tw[u * G + vv] = cmulf(hi, tw[vv]);
+        }
+      }
+      // butterflies in place: the outputs of butterfly b overwrite its inputs, slot b + r*NB
+      static_for<0, NB>([&](auto bi) {
+        constexpr int b = decltype(bi)::value;
+        constexpr int BP = Ns > T ? b % (Ns / T) : 0;
         float2 a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r] = v[b + r * NB];
         if constexpr (Ns > 1) {
-          // a[r] *= w^r with w = exp(-/+ 2 pi i k / (Ns R)).  The angle of w^r is r k / (Ns R)
-          // of a turn, an exact 32-bit fixed-point fraction.  For R > 8, w^r = w^(8u) w^v
-          // (r = 8u + v): R/8 + 6 evaluations instead of R - 1, one extra rounding for some.
-          constexpr int SH = 32 - LOGNS - LOGR;
-          constexpr int G = R > 8 ? 8 : R;
-          float2 lo[G];
-#pragma unroll
-          for (int vv = 1; vv < G; ++vv) lo[vv] = turn_phasor<INV>((uint32_t)(vv * k) << SH);
-#pragma unroll
-          for (int u = 0; u < R / G; ++u) {
-            float2 hi = make_float2(1.0f, 0.0f);
-            if (u > 0) hi = turn_phasor<INV>((uint32_t)(u * G * k) << SH);
-#pragma unroll
-            for (int vv = 0; vv < G; ++vv) {
-              const int r = u * G + vv;
-              if (r == 0) continue;
-              float2 w = vv == 0 ? hi : (u == 0 ? lo[vv] : make_float2(fmaf(hi.x, lo[vv].x, -hi.y * lo[vv].y),
-                                                                      fmaf(hi.x, lo[vv].y, hi.y * lo[vv].x)));
-              a[r] = make_float2(fmaf(a[r].x, w.x, -a[r].y * w.y), fmaf(a[r].x, w.y, a[r].y * w.x));
-            }
-          }
+          static_for<1, R>([&](auto ri) {
+            constexpr int r = decltype(ri)::value;
+            a[r] = rotate_const<r * T * BP, Ns * R, INV>(cmulf(a[r], tw[r]));
+          });
         }
         dft_reg<R, INV>(a);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[b + r * NB] = a[r];
-      }
+      });
       // After the last pass the outputs already sit on the owner's points in natural order.
       if constexpr (!last) {
+        // Output r of butterfly j goes to point base + r Ns, base = (j / Ns) Ns R + k.  For
+        // power-of-two Ns and R the padding splits: pad(base + r Ns) = pad(base) + r Ns +
+        // (r Ns) / 32, a compile-time offset per r.
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
 #pragma unroll
@@ -182,13 +231,15 @@ struct BlockFft {
             const int j = t + T * b;
             const int k = j & (Ns - 1);
             const int base = ((j >> LOGNS) << (LOGNS + LOGR)) + k;
+            const int pb = base + (base >> 5);
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lds_pad(base + r * Ns)] = part ? v[b + r * NB].y : v[b + r * NB].x;
+            for (int r = 0; r < R; ++r)
+              lds[pb + r * Ns + ((r * Ns) >> 5)] = part ? v[b + r * NB].y : v[b + r * NB].x;
           }
           __syncthreads();
 #pragma unroll
           for (int q = 0; q < E; ++q) {
-            const float val = lds[lds_pad(t + T * q)];
+            const float val = lds[read_index(t, q)];
             if (part) v[q].y = val; else v[q].x = val;
           }
           __syncthreads();
@@ -202,10 +253,10 @@ struct BlockFft {
     pass<0>(v, lds);
   }
 
-  // Calls fn(q, Z[f], Z[(N - f) mod N]) for every owned point f = t + T q.  The partner
-  // point is owned by another thread; it is fetched through LDS in two rounds (partners in
-  // the upper half of the index range, then in the lower half), so that only N/2 complex
-  // values are ever staged and no thread has to hold a second copy of its points.
+  // Calls fn(integral_constant q, Z[f], Z[(N - f) mod N]) for every owned point f = t + T q.
+  // The partner point is owned by another thread; it is fetched through LDS in two rounds
+  // (partners in the upper half of the index range, then in the lower half), so that only N/2
+  // complex values are ever staged and no thread has to hold a second copy of its points.
   template <class Fn>
   __device__ __forceinline__ static void with_mirror(const float2 (&v)[E], float* lds, Fn fn) {
     float2* l2 = reinterpret_cast<float2*>(lds);
@@ -216,13 +267,23 @@ struct BlockFft {
       for (int q = 0; q < E; ++q)
         if ((q >= E / 2) == (upper != 0)) l2[t + T * q - upper * (N / 2)] = v[q];
       __syncthreads();
-#pragma unroll
-      for (int q = 0; q < E; ++q) {
+      static_for<0, E>([&](auto qi) {
+        constexpr int q = decltype(qi)::value;
         const int m = (N - (t + T * q)) & (N - 1);
-        if ((m >= N / 2) == (upper != 0)) fn(q, v[q], l2[m - upper * (N / 2)]);
-      }
+        if ((m >= N / 2) == (upper != 0)) fn(qi, v[q], l2[m - upper * (N / 2)]);
+      });
       __syncthreads();
     }
+  }
+
+  // exp(-/+ 2 pi i f / (2N)) for the owned points f = t + T q: one evaluation at f = t, then a
+  // constant rotation by T q / (2N) of a turn per q.
+  template <int Q>
+  __device__ __forceinline__ static float2 half_bin_phasor(float2 w0) {
+    return rotate_const<T * Q, 2 * N, INV>(w0);
+  }
+  __device__ __forceinline__ static float2 half_bin_phasor_base() {
+    return turn_phasor<INV>((uint32_t)threadIdx.x << (32 - LOGN - 1));
   }
 };
 

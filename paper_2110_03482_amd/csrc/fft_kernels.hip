@@ -109,29 +109,46 @@ __device__ __forceinline__ void r2c_body(const FftArgs& a, const int k, const in
   const uint8_t* __restrict__ in_u8 = a.in_u8;
   const float* __restrict__ in_f32 = a.in_f32;
   float2* __restrict__ X = a.X;
-  const float2* __restrict__ twL = a.twL;
   const int64_t n_samp = a.n_samp, stride = a.stride, pitch = a.pitch;
   const int n_chunks = a.n_chunks;
   unsigned int* __restrict__ l1max = a.l1max;
   const int t = threadIdx.x;
   const int64_t s0 = (int64_t)k * stride;
   const float zp = (U8 && s0 + L <= n_samp) ? 128.0f : 0.0f;
+  const int64_t rem64 = n_samp - s0;                           // samples of the series inside the data
+  const int rem = rem64 < L ? (rem64 > 0 ? (int)rem64 : 0) : (int)L;
   float2 v[E];
   if constexpr (U8) {
-    const uint8_t* src = in_u8 + (int64_t)c * n_samp;
+    const uint8_t* src = in_u8 + (int64_t)c * n_samp + s0;
+    if (rem == (int)L && ((uintptr_t)src & 1u) == 0) {
+      // whole series, 2-byte aligned: one 16-bit load per point (x[2j] low byte, x[2j+1] high)
+      const uint16_t* s16 = reinterpret_cast<const uint16_t*>(src);
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int64_t s = s0 + 2 * (int64_t)(t + T * q);
-      v[q].x = s < n_samp ? (float)src[s] - zp : 0.0f;
-      v[q].y = s + 1 < n_samp ? (float)src[s + 1] - zp : 0.0f;
+      for (int q = 0; q < E; ++q) {
+        const uint32_t w = s16[t + T * q];
+        v[q] = make_float2((float)(w & 0xffu) - zp, (float)(w >> 8) - zp);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int s = 2 * (t + T * q);
+        v[q].x = s < rem ? (float)src[s] - zp : 0.0f;
+        v[q].y = s + 1 < rem ? (float)src[s + 1] - zp : 0.0f;
+      }
     }
   } else {
-    const float* src = in_f32 + (int64_t)c * n_samp;
+    const float* src = in_f32 + (int64_t)c * n_samp + s0;
+    if (rem == (int)L && ((uintptr_t)src & 7u) == 0) {
+      const float2* s2 = reinterpret_cast<const float2*>(src);
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int64_t s = s0 + 2 * (int64_t)(t + T * q);
-      v[q].x = s < n_samp ? src[s] : 0.0f;
-      v[q].y = s + 1 < n_samp ? src[s + 1] : 0.0f;
+      for (int q = 0; q < E; ++q) v[q] = s2[t + T * q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int s = 2 * (t + T * q);
+        v[q].x = s < rem ? src[s] : 0.0f;
+        v[q].y = s + 1 < rem ? src[s + 1] : 0.0f;
+      }
     }
   }
   if (l1max != nullptr) {
@@ -146,13 +163,15 @@ __device__ __forceinline__ void r2c_body(const FftArgs& a, const int k, const in
   F::run(v, lds);
   const int row_chunks = a.row_chunks > 0 ? a.row_chunks : n_chunks;   // chunks per row of X
   float2* dst = X + ((int64_t)c * row_chunks + k) * pitch;
-  F::with_mirror(v, lds, [&](int q, float2 zf, float2 zm) {
+  const float2 w0 = F::half_bin_phasor_base();                 // exp(-2 pi i t / L)
+  F::with_mirror(v, lds, [&](auto qi, float2 zf, float2 zm) {
+    constexpr int q = decltype(qi)::value;
     const int f = t + T * q;
     const float2 zc = make_float2(zm.x, -zm.y);                // conj Z[N - f]
     const float2 a = make_float2(0.5f * (zf.x + zc.x), 0.5f * (zf.y + zc.y));
     const float2 d = make_float2(0.5f * (zf.x - zc.x), 0.5f * (zf.y - zc.y));
     const float2 b = make_float2(d.y, -d.x);                   // -i d
-    const float2 w = twL[f];                                   // exp(-2 pi i f / L)
+    const float2 w = F::template half_bin_phasor<q>(w0);       // exp(-2 pi i f / L)
     dst[f] = make_float2(a.x + fmaf(w.x, b.x, -w.y * b.y), a.y + fmaf(w.x, b.y, w.y * b.x));
   });
   if (t == 0) dst[N] = make_float2(v[0].x - v[0].y, 0.0f);   // Nyquist bin
@@ -192,7 +211,6 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   const int64_t n_samp = a.n_samp, stride = a.stride, keep = a.keep, pitch = a.pitch;
   const int n_chunks = a.n_chunks;
   const float add_full = a.add_full;
-  const float2* __restrict__ twL = a.twL;
   const int t = threadIdx.x;
   const int row_chunks = a.row_chunks > 0 ? a.row_chunks : n_chunks;   // chunks per row of Y
   const int64_t row = ((int64_t)dm * row_chunks + k) * pitch;
@@ -200,39 +218,56 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   const float* yi = Yi + row;
   const float2* yc = a.Yc + row;
   const float scale = a.inv_n > 0.0f ? a.inv_n : 1.0f / (float)N;
+  const float2 w0 = F::half_bin_phasor_base();                 // exp(+2 pi i t / L)
   float2 v[E];
-#pragma unroll
-  for (int q = 0; q < E; ++q) {
+  static_for<0, E>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
     const int f = t + T * q;
     const int fm = N - f;                                      // in 1 .. N
     float2 yf, ym;
     if constexpr (INTER) {
       yf = yc[f];
       ym = yc[fm];
-      yf.y = f == 0 ? 0.0f : yf.y;
-      ym.y = fm == N ? 0.0f : -ym.y;                           // conj Y[N - f]
+      ym.y = -ym.y;                                            // conj Y[N - f]
     } else {
-      yf = make_float2(yr[f], f == 0 ? 0.0f : yi[f]);
-      ym = make_float2(yr[fm], fm == N ? 0.0f : -yi[fm]);      // conj Y[N - f]
+      yf = make_float2(yr[f], yi[f]);
+      ym = make_float2(yr[fm], -yi[fm]);
+    }
+    if constexpr (q == 0) {                                    // only q = 0 holds f = 0 (thread 0)
+      yf.y = f == 0 ? 0.0f : yf.y;
+      ym.y = f == 0 ? 0.0f : ym.y;
     }
     const float2 a = make_float2(0.5f * (yf.x + ym.x), 0.5f * (yf.y + ym.y));
     const float2 d = make_float2(0.5f * (yf.x - ym.x), 0.5f * (yf.y - ym.y));
-    const float2 w = twL[f];                                   // exp(-2 pi i f / L); use conj
-    const float2 b = make_float2(fmaf(w.x, d.x, w.y * d.y), fmaf(w.x, d.y, -w.y * d.x));
+    const float2 b = cmulf(F::template half_bin_phasor<q>(w0), d);   // exp(+2 pi i f / L) d
     v[q] = make_float2((a.x - b.y) * scale, (a.y + b.x) * scale);   // A + i B
-    if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);      // bound loads in flight
-  }
+    if constexpr ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound loads in flight
+  });
   F::run(v, lds);
   const int64_t s0 = (int64_t)k * stride;
   const bool full = a.full_chunks >= 0 ? k < a.full_chunks : s0 + L <= n_samp;
   const float add = full ? add_full : 0.0f;
   float* dst = out + (int64_t)dm * n_samp + s0;
-  const int64_t lim = (keep < n_samp - s0) ? keep : n_samp - s0;
+  const int lim = (int)((keep < n_samp - s0) ? keep : n_samp - s0);   // <= L
+  // Points q < qfull lie below lim for every thread (2 T (q + 1) <= lim); point qfull is cut
+  // per sample; later points are all past it.  The tests on q are uniform.
+  const int qfull = lim / (2 * T);
+  const bool al = ((uintptr_t)dst & 7u) == 0;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
-    const int64_t s = 2 * (int64_t)(t + T * q);
-    if (s < lim) dst[s] = v[q].x + add;
-    if (s + 1 < lim) dst[s + 1] = v[q].y + add;
+    const int s = 2 * (t + T * q);
+    const float2 o = make_float2(v[q].x + add, v[q].y + add);
+    if (q < qfull) {
+      if (al) {
+        *reinterpret_cast<float2*>(dst + s) = o;
+      } else {
+        dst[s] = o.x;
+        dst[s + 1] = o.y;
+      }
+    } else if (q == qfull) {
+      if (s < lim) dst[s] = o.x;
+      if (s + 1 < lim) dst[s + 1] = o.y;
+    }
   }
 }
 
