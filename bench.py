@@ -90,7 +90,7 @@ def measured_traffic(kernel: str, workload: str):
 
 def make_paper_input(w, fdd):
     import workloads as W
-    log("generating 8-bit input (2^20 x 1024) ...")
+    log(f"generating 8-bit input ({w.n_samp} x {w.n_chan}) ...")
     x = W.gaussian_u8(w.n_samp, w.n_chan, w.seed)
     for dm, t0 in ((100.0, 1 << 18), (450.0, 1 << 19), (900.0, 3 << 18)):
         tau = fdd.fdd_dispersion_delays(w.freqs, w.ref_freq_mhz, w.tsamp_s, dm)
@@ -472,6 +472,8 @@ def main() -> int:
                     help="all: FP32 (reported as value) plus both split forms")
     ap.add_argument("--mode", default="exact", choices=["exact", "round"])
     ap.add_argument("--n-dm", type=int, default=2048)
+    ap.add_argument("--log-samp", type=int, default=20,
+                    help="paper workload: log2 of the samples per channel (21 doubles the band to 42 chunks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=64, help="trial DMs in the oracle sample")
     ap.add_argument("--cpu-workers", type=int, default=16, help="oracle worker processes (at most the host's CPUs)")
@@ -500,6 +502,9 @@ def main() -> int:
     ref = None
     if paper:
         w = W.paper_shaped_u8(0, n_dm=args.n_dm)
+        if args.log_samp != 20:
+            w.n_samp = 1 << args.log_samp
+            w.name = f"paper_u8_1024ch_2p{args.log_samp}s_{args.n_dm}dm"
         x = make_paper_input(w, fdd)
         if not args.no_cpu_baseline:
             # forked oracle workers start before anything touches the GPU

@@ -106,6 +106,8 @@ struct Launch {
   std::vector<int> beams;     // beams (transpose, FFT stages) or stacks (phasor stage)
   size_t args = 0, prefix = 0;   // descriptor buffer offsets
   size_t ctr = 0;             // phasor stage: word index of its 8 ticket counters
+  int slots = 0;              // descriptors room: beams, or the stacks' chunk groups (phasor stage)
+  int n_desc = 0;             // descriptors written for the current choice
   int total = 0;
 };
 
@@ -197,7 +199,9 @@ const Choice& chosen(const fdd_batch_s* b, const Launch& l) {
 // DM-factorised kernels (uniform DM grid, exact delays).  cands[0] is what fdd_execute runs.
 Class make_class(const fdd_plan_s* p, int N, bool fac, bool fac_default) {
   Class c;
-  c.nt = (2 * N + 15) / 16;
+  // the direct matrix-core kernels run over chunk groups of at most kDirectMaxChunks
+  const int NG = chunk_group_max(N);
+  c.nt = (2 * NG + 15) / 16;
   char key[112];
   const int prec = p->desc.precision;
   const char* fs = fac_default ? "+fac0" : fac ? "+fac" : "";
@@ -210,11 +214,8 @@ Class make_class(const fdd_plan_s* p, int N, bool fac, bool fac_default) {
   } else if (N == 1) {
     std::snprintf(key, sizeof key, "fp32/L%lld/n1%s", (long long)p->L, fs);
     c.cands.push_back({kValu, 1, false});
-  } else if (N > 24) {
-    std::snprintf(key, sizeof key, "fp32/L%lld/valu%s", (long long)p->L, fs);
-    c.cands.push_back({kValu, 4, false});
   } else {
-    const bool small = !phasor_mfma_f32_supported(N);   // the single plan keeps these on the VALU
+    const bool small = !phasor_mfma_f32_supported(NG);   // the single plan keeps these on the VALU
     std::snprintf(key, sizeof key, "fp32/L%lld/%s%d%s", (long long)p->L, small ? "n" : "nt", small ? N : c.nt, fs);
     if (small) c.cands.push_back({kValu, 4, false});
     else
@@ -268,8 +269,8 @@ fdd_status fill(fdd_batch_s* b, const void* const* in, float* const* out) {
     if (l.stage == kTranspose) continue;
     int64_t acc = 0;
     int* prefix = (int*)(b->h_desc.data() + l.prefix);
+    int nd = 0;                                     // descriptors written
     for (size_t i = 0; i < l.beams.size(); ++i) {
-      prefix[i] = (int)acc;
       int64_t tiles = 0;
       if (l.stage == kPhasor) {
         const Stack& sk = b->stacks[(size_t)l.beams[i]];
@@ -297,10 +298,30 @@ fdd_status fill(fdd_batch_s* b, const void* const* in, float* const* out) {
           a.n_coarse = sk.coarse;
           a.n_fine = sk.fine;
           tiles = phasor_fac_tiles(&a, d.precision);
-        } else if (ch.kind == kMfmaF32) tiles = phasor_mfma_f32_tiles(&a, ch.variant);
-        else if (ch.kind == kValu) tiles = phasor_valu_tiles(&a, ch.variant);
-        else tiles = phasor_split_tiles(&a);
-        std::memcpy(b->h_desc.data() + l.args + i * sizeof(PhasorArgs), &a, sizeof a);
+        } else if (ch.kind == kValu) {
+          tiles = phasor_valu_tiles(&a, ch.variant);
+        } else {
+          // direct matrix-core kernels: one descriptor per chunk group
+          const int ng = chunk_groups(a.n_chunks);
+          for (int g = 0; g < ng; ++g) {
+            PhasorArgs t = chunk_group_args(a, g);
+            const int64_t tg = ch.kind == kMfmaF32 ? phasor_mfma_f32_tiles(&t, ch.variant) : phasor_split_tiles(&t);
+            if (g + 1 == ng) {
+              a = t;
+              tiles = tg;
+              break;
+            }
+            prefix[nd] = (int)acc;
+            std::memcpy(b->h_desc.data() + l.args + (size_t)nd * sizeof(PhasorArgs), &t, sizeof t);
+            ++nd;
+            acc += tg;
+            if (acc > std::numeric_limits<int>::max())
+              return fail(FDD_E_UNSUPPORTED, "too many tiles in one grouped launch");
+          }
+        }
+        prefix[nd] = (int)acc;
+        std::memcpy(b->h_desc.data() + l.args + (size_t)nd * sizeof(PhasorArgs), &a, sizeof a);
+        ++nd;
       } else {
         const Beam& bm = b->beams[(size_t)l.beams[i]];
         const Stack& sk = b->stacks[(size_t)bm.stack];
@@ -330,12 +351,15 @@ fdd_status fill(fdd_batch_s* b, const void* const* in, float* const* out) {
           f.add_full = d.input == FDD_IN_U8_TIME_MAJOR ? 128.0f * (float)d.n_chan : 0.0f;
         }
         tiles = fft_grouped_tiles(f);
-        std::memcpy(b->h_desc.data() + l.args + i * sizeof(FftArgs), &f, sizeof f);
+        prefix[nd] = (int)acc;
+        std::memcpy(b->h_desc.data() + l.args + (size_t)nd * sizeof(FftArgs), &f, sizeof f);
+        ++nd;
       }
       acc += tiles;
       if (acc > std::numeric_limits<int>::max()) return fail(FDD_E_UNSUPPORTED, "too many tiles in one grouped launch");
     }
-    prefix[l.beams.size()] = (int)acc;
+    prefix[nd] = (int)acc;
+    l.n_desc = nd;
     l.total = (int)acc;
   }
   return FDD_OK;
@@ -347,7 +371,6 @@ fdd_status upload(fdd_batch_s* b) {
 }
 
 hipError_t enqueue_launch(fdd_batch_s* b, const Launch& l, const void* const* in, hipStream_t st) {
-  const int n = (int)l.beams.size();
   switch (l.stage) {
     case kTranspose: {
       const Beam& bm = b->beams[(size_t)l.beams[0]];
@@ -360,7 +383,7 @@ hipError_t enqueue_launch(fdd_batch_s* b, const Launch& l, const void* const* in
       Group<FftArgs> g;
       g.beams = (const FftArgs*)(b->d_desc + l.args);
       g.prefix = (const int*)(b->d_desc + l.prefix);
-      g.n_beams = n;
+      g.n_beams = l.n_desc;
       g.total = l.total;
       return l.stage == kR2c ? launch_r2c_grouped(l.log_n, l.u8, g, st) : launch_c2r_grouped(l.log_n, g, st);
     }
@@ -369,7 +392,7 @@ hipError_t enqueue_launch(fdd_batch_s* b, const Launch& l, const void* const* in
       g.beams = (const PhasorArgs*)(b->d_desc + l.args);
       g.prefix = (const int*)(b->d_desc + l.prefix);
       g.counters = b->d_small + l.ctr;
-      g.n_beams = n;
+      g.n_beams = l.n_desc;
       g.total = l.total;
       const Choice& ch = chosen(b, l);
       const int nt = b->classes[(size_t)l.cls].nt;
@@ -695,10 +718,12 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
   for (Launch& l : b->launches) {
     if (l.stage == kTranspose) continue;
     const size_t each = l.stage == kPhasor ? sizeof(PhasorArgs) : sizeof(FftArgs);
+    l.slots = 0;
+    for (int i : l.beams) l.slots += l.stage == kPhasor ? chunk_groups(b->stacks[(size_t)i].n_chunks) : 1;
     l.args = doff;
-    doff = align_up(doff + each * l.beams.size());
+    doff = align_up(doff + each * (size_t)l.slots);
     l.prefix = doff;
-    doff = align_up(doff + sizeof(int) * (l.beams.size() + 1));
+    doff = align_up(doff + sizeof(int) * ((size_t)l.slots + 1));
   }
   b->h_desc.assign(doff, 0);
 

@@ -98,6 +98,19 @@ PhasorArgs segment_args(fdd_plan_t p, const PhasorArgs& all, const Segment& sg, 
   return a;
 }
 
+// The direct matrix-core phasor sums (Eq. 7 batched over the overlap-save chunks), one launch
+// per chunk group.
+hipError_t launch_direct(fdd_plan_t p, const PhasorArgs& a, hipStream_t st) {
+  const int ng = chunk_groups(a.n_chunks);
+  for (int g = 0; g < ng; ++g) {
+    const PhasorArgs t = chunk_group_args(a, g);
+    const hipError_t e = p->kernel == "mfma_f32" ? launch_phasor_mfma_f32(t, st)
+                                                 : launch_phasor_split(t, p->kernel == "mfma_bf16_split", st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // The direct split kernels read X as split words: convert it once for all segments.
 hipError_t presplit(fdd_plan_t p, hipStream_t st) {
   if (p->fac_fine > 0 || (p->kernel != "mfma_f16_split" && p->kernel != "mfma_bf16_split")) return hipSuccess;
@@ -190,9 +203,8 @@ fdd_status execute_body(fdd_plan_t p, const void* in, float* out, hipStream_t st
     const PhasorArgs a = segment_args(p, all, sg, false);
     if (p->facw_nt > 0) e = launch_phasor_facw(a, p->desc.precision, p->facw_nt, st);
     else if (p->fac_fine > 0) e = launch_phasor_fac(a, p->desc.precision, st);
-    else if (p->kernel == "mfma_f32") e = launch_phasor_mfma_f32(a, st);
-    else if (p->kernel == "mfma_f16_split") e = launch_phasor_split(a, false, st);
-    else if (p->kernel == "mfma_bf16_split") e = launch_phasor_split(a, true, st);
+    else if (p->kernel == "mfma_f32" || p->kernel == "mfma_f16_split" || p->kernel == "mfma_bf16_split")
+      e = launch_direct(p, a, st);
     else e = launch_phasor_valu(a, st);
     if (e != hipSuccess) return hip_fail(e, "phasor-sum launch");
   }

@@ -78,6 +78,11 @@ struct PhasorArgs {
   const uint4* vtab = nullptr;
   int n_coarse = 0;
   int n_fine = 0;
+  // Chunk tiling of the direct matrix-core kernels: chunks per row of X and of the Y planes
+  // (0: n_chunks).  A launch over chunks k0 .. k0 + n_chunks - 1 of a wider plan has X, Yr, Yi
+  // and l1max offset by k0 chunks and these set to the plan's chunk count.
+  int x_chunks = 0;
+  int y_chunks = 0;
 };
 
 // Spin-frequency-scaled DMs (Eq. 8) for power spectra of one chunk.  Block b covers bins
@@ -232,6 +237,36 @@ hipError_t launch_split_x(float2* X, const unsigned int* l1max, int n_chan, int 
                           hipStream_t st);
 bool phasor_mfma_f32_supported(int n_chunks);
 bool phasor_split_supported(int n_chunks);
+
+// Chunk tiling of the direct matrix-core kernels, which hold at most kDirectMaxChunks chunks
+// (2 x 24 real columns) per workgroup: a plan with more chunks runs them over balanced chunk
+// groups, group g covering chunks k0 .. k0 + cnt - 1.
+constexpr int kDirectMaxChunks = 24;
+inline int chunk_groups(int n_chunks) {
+  return n_chunks <= kDirectMaxChunks ? 1 : (n_chunks + kDirectMaxChunks - 1) / kDirectMaxChunks;
+}
+inline int chunk_group_max(int n_chunks) {
+  const int g = chunk_groups(n_chunks);
+  return (n_chunks + g - 1) / g;
+}
+// The arguments of chunk group g of a (whole-plan) launch a: X, the Y planes and the chunk
+// scales offset by k0 chunks, rows strided by the plan's chunk count.
+inline PhasorArgs chunk_group_args(const PhasorArgs& a, int g) {
+  const int n = a.n_chunks, ng = chunk_groups(n);
+  if (ng == 1) return a;
+  const int k0 = g * (n / ng) + (g < n % ng ? g : n % ng);
+  const int cnt = n / ng + (g < n % ng ? 1 : 0);
+  PhasorArgs t = a;
+  const size_t off = (size_t)k0 * (size_t)a.pitch;
+  t.n_chunks = cnt;
+  t.x_chunks = n;
+  t.y_chunks = n;
+  t.X = a.X + off;
+  if (a.Yr != nullptr) t.Yr = a.Yr + off;
+  if (a.Yi != nullptr) t.Yi = a.Yi + off;
+  if (a.l1max != nullptr) t.l1max = a.l1max + k0;
+  return t;
+}
 // DM-factorised kernels: fine DMs per coarse row for n_chunks chunks (0 if not supported), and
 // the launch (precision: fdd_precision) of a Y-plane or power-spectrum phasor sum.
 int phasor_fac_fine(int n_chunks);

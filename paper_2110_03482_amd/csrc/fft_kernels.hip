@@ -219,29 +219,48 @@ __device__ __forceinline__ void c2r_body(const FftArgs& a, const int k, const in
   const float2* yc = a.Yc + row;
   const float scale = a.inv_n > 0.0f ? a.inv_n : 1.0f / (float)N;
   const float2 w0 = F::half_bin_phasor_base();                 // exp(+2 pi i t / L)
+  // Bins are read in groups of QG points, double-buffered: the loads of group g + 1 are in
+  // flight while group g is split, so the reads are not serialised on memory latency.
+  constexpr int QG = E < 8 ? E : 8;
+  constexpr int NG = E / QG;
+  float2 bf[2][QG], bm[2][QG];                                 // Y[f], Y[N - f]
+  auto load_group = [&](auto gi) {
+    constexpr int g = decltype(gi)::value;
+    static_for<0, QG>([&](auto ui) {
+      constexpr int u = decltype(ui)::value;
+      const int f = t + T * (g * QG + u);
+      const int fm = N - f;                                    // in 1 .. N
+      if constexpr (INTER) {
+        bf[g & 1][u] = yc[f];
+        bm[g & 1][u] = yc[fm];
+      } else {
+        bf[g & 1][u] = make_float2(yr[f], yi[f]);
+        bm[g & 1][u] = make_float2(yr[fm], yi[fm]);
+      }
+    });
+  };
   float2 v[E];
-  static_for<0, E>([&](auto qi) {
-    constexpr int q = decltype(qi)::value;
-    const int f = t + T * q;
-    const int fm = N - f;                                      // in 1 .. N
-    float2 yf, ym;
-    if constexpr (INTER) {
-      yf = yc[f];
-      ym = yc[fm];
-      ym.y = -ym.y;                                            // conj Y[N - f]
-    } else {
-      yf = make_float2(yr[f], yi[f]);
-      ym = make_float2(yr[fm], -yi[fm]);
-    }
-    if constexpr (q == 0) {                                    // only q = 0 holds f = 0 (thread 0)
-      yf.y = f == 0 ? 0.0f : yf.y;
-      ym.y = f == 0 ? 0.0f : ym.y;
-    }
-    const float2 a = make_float2(0.5f * (yf.x + ym.x), 0.5f * (yf.y + ym.y));
-    const float2 d = make_float2(0.5f * (yf.x - ym.x), 0.5f * (yf.y - ym.y));
-    const float2 b = cmulf(F::template half_bin_phasor<q>(w0), d);   // exp(+2 pi i f / L) d
-    v[q] = make_float2((a.x - b.y) * scale, (a.y + b.x) * scale);   // A + i B
-    if constexpr ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound loads in flight
+  load_group(std::integral_constant<int, 0>{});
+  static_for<0, NG>([&](auto gi) {
+    constexpr int g = decltype(gi)::value;
+    if constexpr (g + 1 < NG) load_group(std::integral_constant<int, g + 1>{});
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, QG>([&](auto ui) {
+      constexpr int u = decltype(ui)::value;
+      constexpr int q = g * QG + u;
+      const int f = t + T * q;
+      float2 yf = bf[g & 1][u];
+      float2 ym = make_float2(bm[g & 1][u].x, -bm[g & 1][u].y);   // conj Y[N - f]
+      if constexpr (q == 0) {                                  // only q = 0 holds f = 0 (thread 0)
+        yf.y = f == 0 ? 0.0f : yf.y;
+        ym.y = f == 0 ? 0.0f : ym.y;
+      }
+      const float2 a = make_float2(0.5f * (yf.x + ym.x), 0.5f * (yf.y + ym.y));
+      const float2 d = make_float2(0.5f * (yf.x - ym.x), 0.5f * (yf.y - ym.y));
+      const float2 b = cmulf(F::template half_bin_phasor<q>(w0), d);   // exp(+2 pi i f / L) d
+      v[q] = make_float2((a.x - b.y) * scale, (a.y + b.x) * scale);   // A + i B
+    });
+    __builtin_amdgcn_sched_barrier(0);
   });
   F::run(v, lds);
   const int64_t s0 = (int64_t)k * stride;

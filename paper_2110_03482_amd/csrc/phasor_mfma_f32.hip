@@ -66,6 +66,8 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int N = a.n_chunks;
+  const int XC = a.x_chunks > 0 ? a.x_chunks : N;   // chunks per row of X and of Y
+  const int YC = a.y_chunks > 0 ? a.y_chunks : N;
   const int nel = KC * N * (FB / 2);
 
   // zero once: padding columns (>= 2N) are never written by the staging below
@@ -85,17 +87,17 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
     const int k = e % N;
     const int fp = (e / N) % (FB / 2);
     const int cl = e / ((FB / 2) * N);
-    goff[j] = (cl * N + k) * (int)a.pitch + fb0 + 2 * fp;     // in float2 units, < 2^31 for N <= 24
+    goff[j] = k * (int)a.pitch + fb0 + 2 * fp;                 // in float2 units, within channel cl's row
     loff[j] = cl * CST + 2 * fp * NCOL + k;
     ccl[j] = e < nel ? cl : KC;                                 // KC marks "no element"
   }
   float4 pf[PER];
   auto fetch = [&](int cb) {
-    const float2* base = a.X + (int64_t)cb * N * a.pitch;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
       pf[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (ccl[j] < KC && cb + ccl[j] < a.n_chan) pf[j] = *(const float4*)(base + goff[j]);
+      if (ccl[j] < KC && cb + ccl[j] < a.n_chan)
+        pf[j] = *(const float4*)(a.X + (int64_t)(cb + ccl[j]) * XC * a.pitch + goff[j]);
     }
   };
   auto deposit = [&](float* bre, float* bim) {
@@ -219,8 +221,8 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
     for (int r = 0; r < 4; ++r) {
       const int dmr = dmt * kDmTile + (wave * MW + m) * 16 + 4 * (lane >> 4) + r;
       if (dmr >= a.n_dm) continue;
-      float* dst = (n < N ? a.Yr + ((int64_t)dmr * N + n) * a.pitch
-                          : a.Yi + ((int64_t)dmr * N + (n - N)) * a.pitch) + fb0;
+      float* dst = (n < N ? a.Yr + ((int64_t)dmr * YC + n) * a.pitch
+                          : a.Yi + ((int64_t)dmr * YC + (n - N)) * a.pitch) + fb0;
 #pragma unroll
       for (int f = 0; f < FB; f += 4)
         *(float4*)(dst + f) =

@@ -57,6 +57,8 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int N = a.n_chunks;
+  const int XC = a.x_chunks > 0 ? a.x_chunks : N;   // chunks per row of X and of Y
+  const int YC = a.y_chunks > 0 ? a.y_chunks : N;
   const int nel = KC * N * (FB / 2);
 
   for (int i = tid; i < PLANEW / 4; i += 256) {
@@ -79,7 +81,7 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
       const int k = e / (KC * (FB / 2));
       const int c = cb + cl;
       pf[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (e < nel && c < a.n_chan) pf[q] = *(const float4*)(a.X + ((int64_t)c * N + k) * a.pitch + fb0 + 2 * fp);
+      if (e < nel && c < a.n_chan) pf[q] = *(const float4*)(a.X + ((int64_t)c * XC + k) * a.pitch + fb0 + 2 * fp);
     }
   };
   auto deposit = [&]() {
@@ -213,8 +215,8 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
     for (int r = 0; r < 4; ++r) {
       const int dmr = dmt * 64 + wave * 16 + 4 * (lane >> 4) + r;
       if (dmr >= a.n_dm) continue;
-      float* dst = (n < N ? a.Yr + ((int64_t)dmr * N + n) * a.pitch
-                          : a.Yi + ((int64_t)dmr * N + (n - N)) * a.pitch) + fb0;
+      float* dst = (n < N ? a.Yr + ((int64_t)dmr * YC + n) * a.pitch
+                          : a.Yi + ((int64_t)dmr * YC + (n - N)) * a.pitch) + fb0;
 #pragma unroll
       for (int f = 0; f < FB; f += 4)
         *(float4*)(dst + f) = make_float4(acc[f][nt][r] * inv, acc[f + 1][nt][r] * inv, acc[f + 2][nt][r] * inv,

@@ -480,15 +480,16 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     delete p;
     return fail(FDD_E_UNSUPPORTED, "grid dimension limit exceeded");
   }
-  p->kernel = (d.precision == FDD_FP32 && phasor_mfma_f32_supported((int)p->n_chunks)) ? "mfma_f32" : "valu";
+  // direct matrix-core kernels, over chunk groups of at most kDirectMaxChunks when there are more
+  p->kernel = (d.precision == FDD_FP32 && phasor_mfma_f32_supported(chunk_group_max((int)p->n_chunks)))
+                  ? "mfma_f32" : "valu";
   // tuning override of the matrix-core tile shape
   if (const char* tv = std::getenv("FDD_TILE_VARIANT")) {
     const int v = std::atoi(tv);
     if (v >= 0 && v <= 4) p->tile_variant = v;
   }
-  // the direct split kernels take 1 to 24 chunks; other counts need a factorised kernel below
   if (d.precision == FDD_FP16_SPLIT || d.precision == FDD_BF16_SPLIT)
-    p->kernel = !phasor_split_supported((int)p->n_chunks) ? ""
+    p->kernel = !phasor_split_supported(chunk_group_max((int)p->n_chunks)) ? ""
                 : d.precision == FDD_FP16_SPLIT ? "mfma_f16_split" : "mfma_bf16_split";
   // DM factorisation: exact delays on a uniform DM grid, few chunks (where the direct kernels
   // leave most matrix-core columns empty).  FDD_FACTOR=0 disables it, FDD_FACTOR=all extends
@@ -534,8 +535,7 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
   }
   if (p->kernel.empty()) {
     delete p;
-    return fail(FDD_E_UNSUPPORTED, "split-precision phasor sums support 1 to 24 chunks unless the DM grid is "
-                                   "uniform with exact delays (DM-factorised kernels)");
+    return fail(FDD_E_UNSUPPORTED, "no phasor-sum kernel takes this plan");
   }
   // spin-frequency-scaled DMs (Eq. 8): first block whose rows stay within the halo
   if (d.flags & FDD_PLAN_SCALED_DM) {

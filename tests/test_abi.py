@@ -177,7 +177,7 @@ def test_kernel_selection():
 def test_chunked_factorised_selection():
     """Chunked plans on uniform grids with exact delays take the DM-factorised chunked kernels in
     split precision, with the column-group width following the chunk count, and at any chunk
-    count (the direct split kernels stop at 24 chunks)."""
+    count."""
     import dataclasses
     seen, chunks = set(), []
     for n_samp in (21900, 15000, 9000, 40000, 90000):
@@ -194,11 +194,20 @@ def test_chunked_factorised_selection():
             assert r.kernel == "mfma_f16_split"
             r.close()
     assert len(seen) >= 2 and max(chunks) > 24, (seen, chunks)
-    # more than 24 chunks without a factorisation: rejected
-    w = W.tiny_random(11, 48, 90000, 2048, 2048, single_chunk=False, input_kind="f32")
-    with pytest.raises(fdd.FddError) as e:
-        _dry(w, precision="fp16_split")
-    assert e.value.status == 3
+
+
+def test_direct_kernels_take_any_chunk_count():
+    """Plans that do not factorise (random DMs, or nearest-sample delays) stay on the direct
+    matrix-core kernels above 24 chunks: those run over balanced groups of at most 24 chunks."""
+    for n_samp in (60000, 90000, 140000):
+        w = W.tiny_random(11, 48, n_samp, 256, 2048, single_chunk=False, input_kind="f32")   # random DMs
+        assert _dry(w).kernel == "mfma_f32"
+        for prec in ("fp16_split", "bf16_split"):
+            p = _dry(w, precision=prec)
+            assert p.geometry.n_chunks > 24 and p.kernel == ("mfma_f16_split" if prec == "fp16_split"
+                                                               else "mfma_bf16_split"), (n_samp, prec, p.kernel)
+            p.close()
+        assert _dry(w, mode="round").kernel == "mfma_f32"
 
 
 def test_batch_rejects_without_device_calls():

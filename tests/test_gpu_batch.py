@@ -33,8 +33,8 @@ BEAMS = [
     (33, 50000, 65, 4096, False, "f32", 10.0, "exact"),  # 13 chunks: 2 column tiles
     (40, 30000, 70, 2048, False, "f32", 6.0, "round"),   # 16 chunks: 2 column tiles
     (28, 40000, 45, 2048, False, "f32", 5.0, "exact"),   # 21 chunks: 3 column tiles
-    (12, 60000, 30, 2048, False, "u8", 2.0, "round"),    # 30 chunks: VALU
-    (8, 70000, 17, 1024, False, "f32", 1.0, "exact"),    # 70 chunks at L = 1024: VALU
+    (12, 60000, 30, 2048, False, "u8", 2.0, "round"),    # 30 chunks: MFMA over 2 chunk groups
+    (8, 70000, 17, 1024, False, "f32", 1.0, "exact"),    # 70 chunks at L = 1024: 3 chunk groups
 ]
 
 
@@ -97,8 +97,7 @@ def test_batch_equals_single_plans_and_oracle(graph):
 
 @pytest.mark.parametrize("precision", [["fp16_split", "bf16_split"]])
 def test_batch_split_precision(precision):
-    specs = [s for s in BEAMS if s[0] not in (12, 8)]          # split kernels take up to 24 chunks
-    beams = make_beams(specs, precision)
+    beams = make_beams(BEAMS, precision)
     xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
     print(f"split batch of {len(beams)} beams", flush=True)
     plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
