@@ -62,6 +62,19 @@ __device__ __forceinline__ void seed_phasor(uint4 e, uint32_t f0, float2* w, flo
   *step = make_float2(__uint_as_float(e.z), __uint_as_float(e.w));
 }
 
+// The same from a per-channel linear entry {inc0.lo, inc0.hi, d.lo, d.hi} for trial j: the
+// increment is inc0 + j d (mod 2^64) and the step phasor is evaluated from its top 32 bits
+// (truncation below 2^-32 of a turn).
+__device__ __forceinline__ void seed_phasor_linear(uint4 e, uint32_t j, uint32_t f0, float2* w, float2* step) {
+  const uint64_t inc = (((uint64_t)e.y << 32) | e.x) + (uint64_t)j * (((uint64_t)e.w << 32) | e.z);
+  const PhaseInc pi = {(uint32_t)(inc >> 32), (uint32_t)inc};
+  float s, c;
+  sincos_turn(phase_at(pi, f0), &s, &c);
+  *w = make_float2(c, s);
+  sincos_turn(pi.hi, &s, &c);
+  *step = make_float2(c, s);
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }

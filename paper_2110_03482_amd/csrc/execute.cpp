@@ -72,6 +72,7 @@ PhasorArgs phasor_args(fdd_plan_t p) {
   a.n_pow_bins = (int)(p->L / 2);
   a.log_len = p->log_len;
   a.tile_variant = p->tile_variant;
+  if (p->lin) a.ltab = (const uint4*)(p->d_ws + p->ws.ltab);
   if (p->fac_fine > 0) {
     a.n_coarse = p->fac_coarse;
     a.n_fine = p->fac_fine;
@@ -85,6 +86,7 @@ PhasorArgs phasor_args(fdd_plan_t p) {
 PhasorArgs segment_args(fdd_plan_t p, const PhasorArgs& all, const Segment& sg, bool power) {
   PhasorArgs a = all;
   a.ptab = all.ptab + sg.tab;
+  a.lin_j0 = sg.j0;
   a.n_dm = sg.n;
   const size_t rows = (size_t)sg.j0 * (size_t)p->n_chunks * (size_t)p->pitch;
   if (power) {

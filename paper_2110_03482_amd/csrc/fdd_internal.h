@@ -83,6 +83,11 @@ struct PhasorArgs {
   // and l1max offset by k0 chunks and these set to the plan's chunk count.
   int x_chunks = 0;
   int y_chunks = 0;
+  // Exact delays on a uniform DM grid (direct FP32 kernel): the increment of trial j is
+  // inc0_c + (j + lin_j0) d_c (mod 2^64) from ltab[c] = {inc0.lo, inc0.hi, d.lo, d.hi}; ptab is
+  // then not read.
+  const uint4* ltab = nullptr;
+  int lin_j0 = 0;
 };
 
 // Spin-frequency-scaled DMs (Eq. 8) for power spectra of one chunk.  Block b covers bins
@@ -330,6 +335,7 @@ struct WorkspaceLayout {
   size_t l1 = 0, l1_bytes = 0;        // long transforms: per-series L1 sums
   size_t dtab = 0, dtab_bytes = 0;    // int [n_chan][n_dm] nearest-sample delays (time-domain path)
   size_t ctab = 0, ctab_bytes = 0;    // scaled DMs: uint4 [n_chan] phase increments
+  size_t ltab = 0, ltab_bytes = 0;    // linear phase increments: uint4 [n_chan] (uniform grid, exact delays)
   size_t dmv = 0, dmv_bytes = 0;      // scaled DMs: double [n_dm] trial DMs
   size_t Q = 0, Q_bytes = 0;          // scaled DMs: float [n_dm + 64][q_pitch]
   size_t total = 0;
@@ -352,6 +358,7 @@ struct fdd_plan_s {
   // DM factorisation (uniform DM grid, exact delays): trial j = a * fac_fine + b
   int fac_fine = 0, fac_coarse = 0;     // 0: not factorised
   int facw_nt = 0;                      // > 0: the chunked factorised kernels with this many column tiles
+  bool lin = false;                     // direct FP32 kernel with per-channel linear increments (ltab)
   int tdd_span = 0;                     // largest delay spread over 8 consecutive DMs (time-domain kernel)
   int tdd_span64 = 0;                   // ... over tdd_tile64() consecutive DMs
   double fac_dm0 = 0.0, fac_step = 0.0;

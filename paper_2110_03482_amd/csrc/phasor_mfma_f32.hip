@@ -41,8 +41,9 @@ constexpr int kXcds = 8;
 }  // namespace
 
 // FB bins per workgroup, KC channels per LDS stage, NT 16-column tiles (2N <= 16 NT),
-// MW 16-DM sub-tiles per wave (64 MW DMs per workgroup).
-template <int NT, int FB, int KC, int MW>
+// MW 16-DM sub-tiles per wave (64 MW DMs per workgroup).  LIN: seeds from the per-channel linear
+// increments (a.ltab) instead of the (channel, DM) phase table.
+template <int NT, int FB, int KC, int MW, bool LIN = false>
 __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const int bid, const int n_dmt,
                                                      const int n_bb,
     const int tid) {
@@ -139,14 +140,19 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
   deposit(bre2[0], bim2[0]);
   __syncthreads();
   int it = 0;
-  // phase-table entries of the lane's (DM, channel) seeds, loaded one group ahead
+  // phase-table entries of the lane's (DM, channel) seeds, loaded one group ahead (with LIN
+  // the channel's linear entry, the same for every DM)
+  auto entry = [&](int c, int m) -> uint4 {
+    if constexpr (LIN) return a.ltab[c];
+    else return a.ptab[(int64_t)c * a.n_dm + dmi[m]];
+  };
   uint4 tn[KC / 4][MW];
 #pragma unroll
   for (int s = 0; s < KC / 4; ++s) {
     int c = 4 * s + cq;
     if (c >= a.n_chan) c = a.n_chan - 1;
 #pragma unroll
-    for (int m = 0; m < MW; ++m) tn[s][m] = a.ptab[(int64_t)c * a.n_dm + dmi[m]];
+    for (int m = 0; m < MW; ++m) tn[s][m] = entry(c, m);
   }
   for (int cb = 0; cb < a.n_chan; cb += KC, ++it) {
     const float* bre = bre2[it & 1];
@@ -161,7 +167,7 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
       int c = cb + KC + 4 * s + cq;
       if (c >= a.n_chan) c = a.n_chan - 1;
 #pragma unroll
-      for (int m = 0; m < MW; ++m) tn[s][m] = a.ptab[(int64_t)c * a.n_dm + dmi[m]];
+      for (int m = 0; m < MW; ++m) tn[s][m] = entry(c, m);
     }
     if (cb + KC < a.n_chan) fetch(cb + KC);   // in flight while this block computes
 #pragma unroll
@@ -172,7 +178,8 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
 #pragma unroll
       for (int m = 0; m < MW; ++m) {
         float2 w, step;
-        seed_phasor(tc[s][m], (uint32_t)fb0, &w, &step);
+        if constexpr (LIN) seed_phasor_linear(tc[s][m], (uint32_t)(dmi[m] + a.lin_j0), (uint32_t)fb0, &w, &step);
+        else seed_phasor(tc[s][m], (uint32_t)fb0, &w, &step);
         float wr[FB], wi[FB];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
@@ -234,9 +241,9 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
 // linear workgroup id; grids are 2-D only to keep each dimension below 2^32 work-items
 __device__ __forceinline__ int linear_block() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
-template <int NT, int FB, int KC, int MW>
+template <int NT, int FB, int KC, int MW, bool LIN>
 __global__ __launch_bounds__(256) void k_phasor_mfma_f32(PhasorArgs a, int n_dmt, int n_bb) {
-  phasor_mfma_f32_body<NT, FB, KC, MW>(a, linear_block(), n_dmt, n_bb, threadIdx.x);
+  phasor_mfma_f32_body<NT, FB, KC, MW, LIN>(a, linear_block(), n_dmt, n_bb, threadIdx.x);
 }
 
 // Batched form: the tiles of every beam of the group, one per workgroup or persistent.
@@ -278,8 +285,8 @@ int persistent_blocks(const void* kernel, int threads, int64_t cap) {
 bool phasor_mfma_f32_supported(int n_chunks) { return n_chunks >= 3 && n_chunks <= 24; }
 
 namespace {
-template <int FB, int KC, int MW>
-hipError_t launch_tile(const PhasorArgs& a, hipStream_t st) {
+template <int FB, int KC, int MW, bool LIN>
+hipError_t launch_tile_lin(const PhasorArgs& a, hipStream_t st) {
   const int n_dmt = (a.n_dm + 64 * MW - 1) / (64 * MW);
   const int n_bb = (a.n_bins + FB - 1) / FB;
   const int n_bb8 = (n_bb + kXcds - 1) / kXcds * kXcds;
@@ -287,12 +294,17 @@ hipError_t launch_tile(const PhasorArgs& a, hipStream_t st) {
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid = linear_grid(blocks), block(256);
   switch ((2 * a.n_chunks + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_phasor_mfma_f32<1, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;
-    case 2: hipLaunchKernelGGL((k_phasor_mfma_f32<2, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;
-    case 3: hipLaunchKernelGGL((k_phasor_mfma_f32<3, FB, KC, MW>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 1: hipLaunchKernelGGL((k_phasor_mfma_f32<1, FB, KC, MW, LIN>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 2: hipLaunchKernelGGL((k_phasor_mfma_f32<2, FB, KC, MW, LIN>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 3: hipLaunchKernelGGL((k_phasor_mfma_f32<3, FB, KC, MW, LIN>), grid, block, 0, st, a, n_dmt, n_bb); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int FB, int KC, int MW>
+hipError_t launch_tile(const PhasorArgs& a, hipStream_t st) {
+  return a.ltab != nullptr ? launch_tile_lin<FB, KC, MW, true>(a, st) : launch_tile_lin<FB, KC, MW, false>(a, st);
 }
 }  // namespace
 

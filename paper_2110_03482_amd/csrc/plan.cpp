@@ -105,7 +105,9 @@ void factor_tables(const fdd_plan_s* p, int fine, int coarse, double dm0, double
   out->insert(out->end(), tb.begin(), tb.end());
 }
 
-// A DM list DM_j = DM_0 + j dDM (to 1e-10 of the largest DM), as numpy.linspace makes it.
+// A DM list DM_j = DM_0 + j dDM (to 1e-12 of the largest DM), as numpy.linspace makes it.  The
+// kernels that use the grid form delays from DM_0 and dDM: a deviation of 1e-12 DM_max moves a
+// phase by at most 1e-12 pi tau_max radians (5e-8 at tau_max = 15000 samples).
 bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step) {
   const size_t n = dms.size();
   if (n < 2) return false;
@@ -114,7 +116,7 @@ bool uniform_grid(const std::vector<double>& dms, double* dm0, double* step) {
   if (!(*step > 0.0)) return false;
   double big = 0.0;
   for (double v : dms) big = std::max(big, std::fabs(v));
-  const double tol = 1e-10 * big;
+  const double tol = 1e-12 * big;
   for (size_t j = 0; j < n; ++j)
     if (std::fabs(dms[j] - (*dm0 + (double)j * *step)) > tol) return false;
   return true;
@@ -147,6 +149,19 @@ static void scaled_table(const fdd_plan_s* p, std::vector<uint4>* out) {
   for (size_t c = 0; c < p->kappa.size(); ++c) {
     uint4 e;
     turn_fraction(first * p->kappa[c], p->log_len, &e.x, &e.y);
+    turn_fraction(p->grid_step * p->kappa[c], p->log_len, &e.z, &e.w);
+    (*out)[c] = e;
+  }
+}
+
+// Linear increments per channel for exact delays on a uniform grid DM_j = DM_0 + j dDM: the turn
+// fraction per bin of trial j is inc0 + j d (mod 2^64), with inc0 from DM_0 kappa_c and d from
+// dDM kappa_c (Eq. 1 is linear in DM).
+static void linear_table(const fdd_plan_s* p, std::vector<uint4>* out) {
+  out->resize(p->kappa.size());
+  for (size_t c = 0; c < p->kappa.size(); ++c) {
+    uint4 e;
+    turn_fraction(p->grid_dm0 * p->kappa[c], p->log_len, &e.x, &e.y);
     turn_fraction(p->grid_step * p->kappa[c], p->log_len, &e.z, &e.w);
     (*out)[c] = e;
   }
@@ -197,6 +212,11 @@ static void build_host_tables(fdd_plan_s* p) {
     scaled_table(p, &ct);
     keep(w.ctab, ct.data(), w.ctab_bytes);
     keep(w.dmv, p->dms.data(), w.dmv_bytes);
+  }
+  if (p->lin) {
+    std::vector<uint4> lt;
+    linear_table(p, &lt);
+    keep(w.ltab, lt.data(), w.ltab_bytes);
   }
 }
 
@@ -285,6 +305,10 @@ static fdd_status layout(fdd_plan_s* p) {
   if (!mul_ok((size_t)d.n_chan * (size_t)d.n_dm, sizeof(int), &w.dtab_bytes))
     return fail(FDD_E_NOMEM, "delay table size overflows");
   put(&w.dtab, w.dtab_bytes);
+  if (p->lin) {
+    w.ltab_bytes = (size_t)d.n_chan * sizeof(uint4);
+    put(&w.ltab, w.ltab_bytes);
+  }
   if (p->scaled) {
     w.ctab_bytes = (size_t)d.n_chan * sizeof(uint4);
     put(&w.ctab, w.ctab_bytes);
@@ -536,6 +560,21 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
   if (p->kernel.empty()) {
     delete p;
     return fail(FDD_E_UNSUPPORTED, "no phasor-sum kernel takes this plan");
+  }
+  // FDD_PHASE_TABLE=linear: the direct FP32 kernel on a uniform grid with exact delays derives
+  // each trial's increment from two per-channel values instead of reading the [n_chan][n_dm]
+  // phase table.  That removes the table's re-reads from memory but adds one sin/cos
+  // evaluation per seed; on the paper-shaped workload the kernel is bound by instruction issue,
+  // not by those reads, and the table is the faster of the two.
+  {
+    const char* pt = std::getenv("FDD_PHASE_TABLE");
+    double dm0 = 0.0, step = 0.0;
+    if (p->kernel == "mfma_f32" && d.delay_mode == FDD_DELAY_EXACT && pt != nullptr && std::strcmp(pt, "linear") == 0 &&
+        uniform_grid(p->dms, &dm0, &step)) {
+      p->lin = true;
+      p->grid_dm0 = dm0;
+      p->grid_step = step;
+    }
   }
   // spin-frequency-scaled DMs (Eq. 8): first block whose rows stay within the halo
   if (d.flags & FDD_PLAN_SCALED_DM) {

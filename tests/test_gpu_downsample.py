@@ -72,6 +72,20 @@ def test_downsampled_matches_oracle(case):
     check(w, x, mode, rows, g, factors, label)
 
 
+def test_downsampled_linear_increments(monkeypatch):
+    """A uniform DM grid with exact delays on the direct FP32 kernel with per-channel linear
+    increments (FDD_PHASE_TABLE=linear): each segment's trials are offset by its first DM index."""
+    import dataclasses
+    w = W.tiny_random(43, 16, 20000, 40, 2048, False, "f32", dm_max=10.0)
+    w = dataclasses.replace(w, dms=np.linspace(0.0, 10.0, 40))
+    x = make_input(w, 5)
+    factors = np.asarray([1] * 10 + [2] * 10 + [4] * 10 + [8] * 10, dtype=np.int32)
+    monkeypatch.setenv("FDD_PHASE_TABLE", "linear")
+    rows, g, kernel = run(w, x, "exact", "fp32", factors)
+    assert kernel == "mfma_f32" and g.n_segments == 4
+    check(w, x, "exact", rows, g, factors, "linear increments, 4 segments")
+
+
 def test_factor_one_everywhere_is_bitwise_full_resolution():
     w = W.tiny_random(41, 16, 20000, 40, 2048, False, "u8", dm_max=10.0)
     x = make_input(w, 4)

@@ -178,19 +178,22 @@ def paper_input():
     return w, x
 
 
-@pytest.mark.parametrize("factor", ["default", "wide"])
+@pytest.mark.parametrize("factor", ["default", "wide", "linear"])
 def test_paper_shaped_sampled_rows(paper_input, factor):
     """1024 ch x 2^20 8-bit samples x 2048 DMs, L = 2^16 (21 chunks): rows checked against the
-    oracle, on the direct FP32 kernel (the default) and on the chunked DM-factorised FP32 kernel
-    (FDD_FACTOR=wide)."""
+    oracle, on the direct FP32 kernel (the default), on the chunked DM-factorised FP32 kernel
+    (FDD_FACTOR=wide) and on the direct kernel with per-channel linear increments
+    (FDD_PHASE_TABLE=linear)."""
     w, x = paper_input
     print(f"paper-shaped workload, exact mode, {factor} kernel", flush=True)
-    if factor == "wide":
-        os.environ["FDD_FACTOR"] = "wide"
+    env = {"wide": ("FDD_FACTOR", "wide"), "linear": ("FDD_PHASE_TABLE", "linear")}.get(factor)
+    if env is not None:
+        os.environ[env[0]] = env[1]
     try:
         y, kernel, g = run_gpu(w, x, "exact")
     finally:
-        os.environ.pop("FDD_FACTOR", None)
+        if env is not None:
+            os.environ.pop(env[0], None)
     assert kernel == ("facw_f32" if factor == "wide" else "mfma_f32") and g.n_chunks == 21
     rows = [0, 1, 921, 1842, 2047]
     ref = run_oracle(w, x, "exact", rows=rows)
