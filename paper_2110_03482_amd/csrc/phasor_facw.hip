@@ -305,7 +305,10 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
 
   // Epilogue: lane (column j < 16 of tile i) holds Re of column q = q0 + 16 i + j for the rows
   // of its registers, the lane 16 apart the Im parts.  One exchange gives each lane both parts
-  // of half of the rows; the scale of chunk k is divided out.
+  // of half of the rows (registers r of a lane j < 16 with registers r of its partner, registers
+  // r + 8 of a lane j >= 16 with those of its partner: v_permlane16_swap of the register pair
+  // (r, r + 8)); the scale of chunk k is divided out.  (A select between acc[r] and acc[r + 8]
+  // would be folded into a run-time register index, lowered as a chain of compares.)
   const int jj = lane & 31;
   const bool lo16 = jj < 16;
 #pragma unroll
@@ -319,9 +322,9 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
       float2 y[FB];
 #pragma unroll
       for (int f = 0; f < FB; ++f) {
-        const float send = lo16 ? acc[f][i][r + 8] : acc[f][i][r];
-        const float recv = __shfl_xor(send, 16, 64);
-        y[f] = lo16 ? make_float2(acc[f][i][r] * inv, recv * inv) : make_float2(recv * inv, acc[f][i][r + 8] * inv);
+        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc[f][i][r]),
+                                                         __float_as_uint(acc[f][i][r + 8]), false, false);
+        y[f] = make_float2(__uint_as_float(sw[0]) * inv, __uint_as_float(sw[1]) * inv);
       }
       const int ar = tl.rt * kWRows + wave * 32 + acc_row(lo16 ? r : r + 8, h);
       const int dm = ar * g.B + b;
@@ -475,10 +478,10 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_f32(PhasorArgs a, int n_
     for (int r = 0; r < 8; ++r) {
       float2 y[FB];
 #pragma unroll
-      for (int f = 0; f < FB; ++f) {
-        const float send = lo16 ? acc[f][i][r + 8] : acc[f][i][r];
-        const float recv = __shfl_xor(send, 16, 64);
-        y[f] = lo16 ? make_float2(acc[f][i][r], recv) : make_float2(recv, acc[f][i][r + 8]);
+      for (int f = 0; f < FB; ++f) {   // the exchange of the split kernel's epilogue
+        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc[f][i][r]),
+                                                         __float_as_uint(acc[f][i][r + 8]), false, false);
+        y[f] = make_float2(__uint_as_float(sw[0]), __uint_as_float(sw[1]));
       }
       const int ar = tl.rt * kWRows + wave * 32 + acc_row(lo16 ? r : r + 8, h);
       const int dm = ar * g.B + b;

@@ -40,7 +40,17 @@ struct HalfMma<true> {
   }
 };
 
+// 1.0f in a scalar register whose value the compiler does not see.  In fma(h, -one, x) with a
+// float16 h this keeps the mixed-precision form (v_fma_mix_f32 takes the half operand as it is
+// packed) instead of the conversion and subtraction that the folded x - h would cost.
+__device__ __forceinline__ float opaque_one() {
+  float one;
+  asm("s_mov_b32 %0, 1.0" : "=s"(one));
+  return one;
+}
+
 // Head/tail split of a pair (x, y): hi = (half(x), half(y)), lo = (half(x - hi_x), half(y - hi_y)).
+// The residuals x - hi_x are exact in float32 (hi_x holds the leading 11 or 8 bits of x).
 template <bool BF>
 __device__ __forceinline__ void split_pair(float x, float y, uint32_t* hi, uint32_t* lo) {
   const float2v v = {x, y};
@@ -52,8 +62,8 @@ __device__ __forceinline__ void split_pair(float x, float y, uint32_t* hi, uint3
     *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf162v));
   } else {
     const half2v h = __builtin_convertvector(v, half2v);
-    const float2v hb = __builtin_convertvector(h, float2v);
-    const float2v r = {x - hb[0], y - hb[1]};
+    const float one = opaque_one();
+    const float2v r = {__builtin_fmaf((float)h[0], -one, x), __builtin_fmaf((float)h[1], -one, y)};
     *hi = __builtin_bit_cast(uint32_t, h);
     *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, half2v));
   }
