@@ -50,8 +50,10 @@ __device__ __forceinline__ float opaque_one() {
 }
 
 // Head/tail split of a pair (x, y): hi = (half(x), half(y)), lo = (half(x - hi_x), half(y - hi_y)).
-// The residuals x - hi_x are exact in float32 (hi_x holds the leading 11 or 8 bits of x).
-template <bool BF>
+// The residuals x - hi_x are exact in float32 (hi_x holds the leading 11 or 8 bits of x).  MIX
+// (float16): the residuals through v_fma_mix_f32; the same values, fewer instructions, though in
+// some kernels more live registers (the factorised power-spectrum kernel loses a wave).
+template <bool BF, bool MIX = true>
 __device__ __forceinline__ void split_pair(float x, float y, uint32_t* hi, uint32_t* lo) {
   const float2v v = {x, y};
   if constexpr (BF) {
@@ -60,10 +62,16 @@ __device__ __forceinline__ void split_pair(float x, float y, uint32_t* hi, uint3
     const float2v r = {x - hb[0], y - hb[1]};
     *hi = __builtin_bit_cast(uint32_t, h);
     *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf162v));
-  } else {
+  } else if constexpr (MIX) {
     const half2v h = __builtin_convertvector(v, half2v);
     const float one = opaque_one();
     const float2v r = {__builtin_fmaf((float)h[0], -one, x), __builtin_fmaf((float)h[1], -one, y)};
+    *hi = __builtin_bit_cast(uint32_t, h);
+    *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, half2v));
+  } else {
+    const half2v h = __builtin_convertvector(v, half2v);
+    const float2v hb = __builtin_convertvector(h, float2v);
+    const float2v r = {x - hb[0], y - hb[1]};
     *hi = __builtin_bit_cast(uint32_t, h);
     *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, half2v));
   }
