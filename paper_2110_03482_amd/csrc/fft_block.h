@@ -184,22 +184,20 @@ struct BlockFft {
       // scales its input r by w^r, w = exp(-/+ 2 pi i k / (Ns R)).  For Ns <= T every b has
       // k0 = t mod Ns; for Ns > T, k = t + T b' with b' = b mod (Ns / T), and the extra factor
       // exp(-/+ 2 pi i r T b' / (Ns R)) is a compile-time constant.  So only the twiddles of k0
-      // are evaluated: the angle r k0 / (Ns R) of a turn is an exact 32-bit fixed-point
-      // fraction; for R > 8 w^r = w^(8u) w^v (r = 8u + v) takes R/8 + 6 evaluations instead of
-      // R - 1, at one extra rounding for some r.
+      // are evaluated: w^(2^e) from the exact 32-bit fixed-point angle 2^e k0 / (Ns R) of a
+      // turn, every other power as a product of those (w^r = w^(2^e) w^(r - 2^e), 2^e the top
+      // bit of r): log2 R evaluations instead of R - 1, at most log2 R - 1 extra roundings.
       float2 tw[R];
       if constexpr (Ns > 1) {
         constexpr int SH = 32 - LOGNS - LOGR;
-        constexpr int G = R > 8 ? 8 : R;
         const uint32_t k0 = (uint32_t)t & (uint32_t)(Ns - 1);
 #pragma unroll
-        for (int vv = 1; vv < G; ++vv) tw[vv] = turn_phasor<INV>((uint32_t)(vv * k0) << SH);
+        for (int r = 1; r < R; r *= 2) tw[r] = turn_phasor<INV>((uint32_t)(r * k0) << SH);
 #pragma unroll
-        for (int u = 1; u < R / G; ++u) {
-          const float2 hi = turn_phasor<INV>((uint32_t)(u * G * k0) << SH);
-          tw[u * G] = hi;
-#pragma unroll
-          for (int vv = 1; vv < G; ++vv) tw[u * G + vv] = cmulf(hi, tw[vv]);
+        for (int r = 3; r < R; ++r) {
+          if ((r & (r - 1)) == 0) continue;
+          const int top = 1 << cx_log2(r);
+          tw[r] = cmulf(tw[top], tw[r - top]);
         }
       }
       // butterflies in place: the outputs of butterfly b overwrite its inputs, slot b + r*NB
