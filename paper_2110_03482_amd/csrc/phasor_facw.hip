@@ -236,27 +236,30 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
 #pragma unroll
   for (int i = 0; i < NT; ++i) deposit(zbase, i);
   fetch(kWKc);
-  // Per stage, the products run as one software-pipelined sequence of steps j = (K-step s, bin f,
-  // tile i): the B operands of step j + 2 are read from LDS while step j's three products run,
-  // the A operands of a block (s, f) are split one step before it, the phasors of K-step 1 are
-  // seeded during K-step 0, and the next stage's staging is spread over the steps.  The body
-  // has no branch, so all of it is one scheduling region.
-  constexpr int NS = 2 * FB * NT;
+  // Per stage, the products run block by block, a block (K-step s, bin f) being NT tiles that
+  // share the A operands: the hi.hi products of all NT tiles, then their hi.lo, then their lo.hi,
+  // so that NT - 1 other products separate two updates of one accumulator (back to back, each
+  // would wait for the previous one and hold up the vector work between them).  The B operands
+  // of the next block are read from LDS while a block's products run, its A operands are split
+  // before it, the phasors of K-step 1 are seeded during K-step 0, and the next stage's staging
+  // is spread over the blocks.  The body has no branch, so all of it is one scheduling region.
   for (int st = 0; st < n_st; ++st) {
     __syncthreads();                         // stage st staged; the other buffer no longer read
     const uint32_t* zr = zbase + (st & 1) * 2 * PW;
     uint32_t* zw = zbase + ((st + 1) & 1) * 2 * PW;
     const int cb = st * kWKc;
     seed_v();                                // V of the next stage (unused after the last)
-    V8 bh[3], bl[3];
-    auto ldb = [&](int j, int r) {
-      const int blk = j / NT, i = j % NT, s = blk / FB, f = blk % FB;
-      const int wo = ((f * NT + i) * 32 + (lane & 31)) * RW + 8 * s + 4 * h;
-      bh[r] = __builtin_bit_cast(V8, *(const uint4*)(zr + wo));
-      bl[r] = __builtin_bit_cast(V8, *(const uint4*)(zr + PW + wo));
+    V8 bh[2][NT], bl[2][NT];
+    auto ldblk = [&](int blk, int r) {
+      const int s = blk / FB, f = blk % FB;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const int wo = ((f * NT + i) * 32 + (lane & 31)) * RW + 8 * s + 4 * h;
+        bh[r][i] = __builtin_bit_cast(V8, *(const uint4*)(zr + wo));
+        bl[r][i] = __builtin_bit_cast(V8, *(const uint4*)(zr + PW + wo));
+      }
     };
-    ldb(0, 0);
-    ldb(1, 1);
+    ldblk(0, 0);
     pin_lds_reads();
     float2 w[4], sp[4], wn[4], spn[4];
 #pragma unroll
@@ -275,9 +278,9 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
     };
     split_a();
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      const int blk = j / NT, i = j % NT, f = blk % FB;
-      if (i == 0 && j > 0) {
+    for (int blk = 0; blk < 2 * FB; ++blk) {
+      const int f = blk % FB, r = blk & 1;
+      if (blk > 0) {
         if (blk == FB) {                     // K-step 1 begins
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
@@ -288,17 +291,22 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
         }
         split_a();
       }
-      if (j == 1) {
+      if (blk == 0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) seed_phasor(tn[4 + u], f0, &wn[u], &spn[u]);
       }
-      if (j + 2 < NS) ldb(j + 2, (j + 2) % 3);
+      if (blk + 1 < 2 * FB) ldblk(blk + 1, r ^ 1);
       pin_lds_reads();
-      const int r = j % 3;
-      acc[f][i] = H::mfma(Ahi, bh[r], acc[f][i]);
-      acc[f][i] = H::mfma(Ahi, bl[r], acc[f][i]);
-      acc[f][i] = H::mfma(Alo, bh[r], acc[f][i]);
-      if (j % 4 == 3 && j / 4 < NT) deposit(zw, j / 4);
+#pragma unroll
+      for (int i = 0; i < NT; ++i) { acc[f][i] = H::mfma(Ahi, bh[r][i], acc[f][i]); }
+      pin_lds_reads();
+      if (blk * 2 < NT) deposit(zw, blk * 2);
+#pragma unroll
+      for (int i = 0; i < NT; ++i) { acc[f][i] = H::mfma(Ahi, bl[r][i], acc[f][i]); }
+      pin_lds_reads();
+      if (blk * 2 + 1 < NT) deposit(zw, blk * 2 + 1);
+#pragma unroll
+      for (int i = 0; i < NT; ++i) { acc[f][i] = H::mfma(Alo, bh[r][i], acc[f][i]); }
     }
     fetch((st + 2) * kWKc);
   }
@@ -525,6 +533,11 @@ hipError_t launch_facw_nt(const PhasorArgs& a, int precision, hipStream_t st) {
 }  // namespace
 
 FacwChoice facw_choose(int n_dm, int n_chunks) {
+  // Time per workgroup tile by column-tile count nt = 4, 5, 6, 7, relative, measured with the
+  // FP16 split kernel on the paper-shaped bin and channel counts (18, 24, 30 and 15 ms per
+  // 128-row group over all bins): the 7-tile shape is the fastest per tile as well as per
+  // column, the others lose more than their share of matrix work.
+  constexpr double kTileCost[kFacwNtMax - kFacwNtMin + 1] = {18.0, 24.0, 30.0, 15.0};
   FacwChoice best;
   double best_cost = 0.0;
   for (int fine : {16, 8}) {
@@ -534,8 +547,7 @@ FacwChoice facw_choose(int n_dm, int n_chunks) {
       const int64_t grp = ((int64_t)fine * n_chunks + 16 * nt - 1) / (16 * nt);
       // useful (trial, chunk) pairs over the padded tile area (coarse rows x columns)
       const double eff = (double)n_dm * n_chunks / ((double)rt * kWRows * (double)grp * 16 * nt);
-      // matrix work per tile ~ nt, plus a fixed share for phasor generation and staging
-      const double cost = (double)rt * (double)grp * (nt + 2.5);
+      const double cost = (double)rt * (double)grp * kTileCost[nt - kFacwNtMin];
       if (best.fine == 0 || cost < best_cost) {
         best.fine = fine;
         best.coarse = coarse;
