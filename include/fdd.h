@@ -258,7 +258,11 @@ fdd_status fdd_batch_create(int32_t n_plans, const fdd_plan_t* plans, const fdd_
  * input and float32 [n_dm][n_samp] output, as for fdd_execute.  The first call (and a call
  * whose pointers differ from the previous call's) synchronises `stream`: it runs the
  * autotuner if needed, writes the launch descriptors and captures the graph.  Other calls
- * enqueue one graph launch and do not synchronise.  Calls on one batch must not overlap.
+ * enqueue one graph launch and do not synchronise.  A call on another stream than the previous
+ * call's makes that stream wait for the previous call (an event, no host wait), and a call that
+ * rewrites the descriptors first waits on the host for every earlier call of the batch; calls
+ * from several host threads at once race.  The batch records events on `stream`, so it is not
+ * meant to be called inside a caller's stream capture.
  * Errors: FDD_E_INVALID, FDD_E_DEVICE. */
 fdd_status fdd_batch_execute(fdd_batch_t batch, const void* const* d_in, float* const* d_out, void* stream);
 

@@ -175,6 +175,9 @@ struct fdd_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
+  hipEvent_t done = nullptr;         // recorded after every call's launches
+  hipStream_t last_st = nullptr;     // stream of the last call
+  bool launched = false;
 };
 
 namespace {
@@ -183,11 +186,13 @@ void release(fdd_batch_s* b) {
   if (b->exec != nullptr) (void)hipGraphExecDestroy(b->exec);
   if (b->graph != nullptr) (void)hipGraphDestroy(b->graph);
   if (b->cap != nullptr) (void)hipStreamDestroy(b->cap);
+  if (b->done != nullptr) (void)hipEventDestroy(b->done);
   for (void* p : {(void*)b->d_tab, (void*)b->d_scr, (void*)b->d_small, (void*)b->d_desc})
     if (p != nullptr) (void)hipFree(p);
   b->exec = nullptr;
   b->graph = nullptr;
   b->cap = nullptr;
+  b->done = nullptr;
 }
 
 const Choice& chosen(const fdd_batch_s* b, const Launch& l) {
@@ -763,6 +768,10 @@ fdd_status fdd_batch_create(int32_t n, const fdd_plan_t* plans, const fdd_batch_
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) s = hip_fail(e, "hipStreamCreate");
   }
+  if (s == FDD_OK) {
+    hipError_t e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) s = hip_fail(e, "hipEventCreate");
+  }
   if (s != FDD_OK) {
     release(b);
     delete b;
@@ -778,11 +787,19 @@ fdd_status fdd_batch_execute(fdd_batch_t b, const void* const* in, float* const*
   for (size_t i = 0; i < n; ++i)
     if (in[i] == nullptr || out[i] == nullptr) return fail(FDD_E_INVALID, "null input or output of beam " + std::to_string(i));
   hipStream_t st = (hipStream_t)stream;
+  // A call on another stream than the last one waits for it: the calls of a batch share the
+  // descriptors and the ticket counters, and a chain of waits lets one event stand for all
+  // earlier calls below.
+  if (b->launched && st != b->last_st) {
+    hipError_t e = hipStreamWaitEvent(st, b->done, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+  }
   const bool same = b->ready && std::equal(in, in + n, b->last_in.begin()) && std::equal(out, out + n, b->last_out.begin());
   if (!same) {
     b->ready = false;
-    hipError_t e = hipStreamSynchronize(st);            // earlier calls still read the descriptors
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    // Earlier calls, on whichever stream, may still read the descriptors about to be rewritten.
+    hipError_t e = b->launched ? hipEventSynchronize(b->done) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     bool tune = false;
     for (const Class& c : b->classes) tune = tune || !c.settled;
     fdd_status s = tune ? autotune(b, in, out, st) : FDD_OK;
@@ -812,9 +829,18 @@ fdd_status fdd_batch_execute(fdd_batch_t b, const void* const* in, float* const*
     b->last_out.assign(out, out + n);
     b->ready = true;
   }
-  if (b->flags & FDD_BATCH_NO_GRAPH) return enqueue_all(b, in, st);
-  hipError_t e = hipGraphLaunch(b->exec, st);
-  return e == hipSuccess ? FDD_OK : hip_fail(e, "hipGraphLaunch");
+  if (b->flags & FDD_BATCH_NO_GRAPH) {
+    const fdd_status s = enqueue_all(b, in, st);
+    if (s != FDD_OK) return s;
+  } else {
+    const hipError_t e = hipGraphLaunch(b->exec, st);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  const hipError_t e = hipEventRecord(b->done, st);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  b->last_st = st;
+  b->launched = true;
+  return FDD_OK;
 }
 
 fdd_status fdd_batch_info(fdd_batch_t b, int32_t* n_waves, size_t* scratch_bytes, size_t* table_bytes) {

@@ -167,6 +167,39 @@ def test_graph_replays_and_recapture():
         p.close()
 
 
+def test_batch_calls_on_two_streams():
+    """Calls of one batch on alternating streams: a call on another stream waits for the previous
+    call (same descriptors and ticket counters), and a call with new tensors waits for all earlier
+    ones before it rewrites the descriptors.  Each call's inputs are rescaled on its own stream
+    just before it, so a call that ran early would read the previous values."""
+    specs = [s for s in BEAMS if s[5] == "f32"][:4]
+    beams = make_beams(specs, seed0=400)
+    xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
+    plans = [plan_of(w, mode, prec, False) for w, _, mode, prec in beams]
+    ref_plans = [plan_of(w, mode, prec, True) for w, _, mode, prec in beams]
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    print("batch calls on two streams", flush=True)
+    with fdd.Batch(plans, autotune=False) as b:
+        outs = [torch.empty((p.n_dm, p.n_samp), dtype=torch.float32, device="cuda") for p in plans]
+        results = []
+        # same tensors on the other stream, new tensors (descriptors rewritten), the first ones again
+        for call, (st, fresh) in enumerate(((sa, False), (sb, False), (sa, True), (sb, False))):
+            st.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st):
+                for x in xs:
+                    x.mul_(-0.5).add_(0.25)
+                ys = b.execute(xs, None if fresh else outs, stream=st)
+                snap = [y.clone() for y in ys]
+            torch.cuda.current_stream().wait_stream(st)
+            eager = [p.execute(x) for p, x in zip(ref_plans, xs)]
+            results.append((call, snap, eager))
+        torch.cuda.synchronize()
+        for call, snap, eager in results:
+            for y, e in zip(snap, eager):
+                assert torch.equal(y, e), f"call {call} differs from the eager result"
+    for p in ref_plans:
+        p.close()
+
 def test_memory_waves():
     beams = make_beams(BEAMS, seed0=500)
     xs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for _, x, _, _ in beams]
