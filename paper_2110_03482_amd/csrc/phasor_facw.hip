@@ -42,6 +42,7 @@ constexpr int kWXcds = 8;
 constexpr int kWRows = 128;   // coarse rows per workgroup
 constexpr int kWKc = 16;      // channels per LDS stage
 constexpr int kWFb = 2;       // bins per workgroup
+constexpr int kWValuPerMfma = 7;   // vector instructions scheduled after each product (split kernels)
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -94,6 +95,34 @@ __device__ __forceinline__ void pin_lds_reads() {
   // VALU 0x002, SALU 0x004, VMEM 0x010/0x020/0x040, DS write 0x200, transcendental 0x400 may
   // cross; not 0x001 (every non-memory instruction, MFMA included), MFMA 0x008 or DS reads
   __builtin_amdgcn_sched_barrier(0x0676);
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads in flight stay in flight (a
+// full barrier would also wait for every outstanding load, among them the staging data of the
+// stage after next).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// sin and cos of 2 pi p / 2^32 from a 256-entry table of the phasors of k / 256 turn (nearest k)
+// and the rotation by the remainder |y| <= pi / 256, whose sine and cosine are y - y^3 / 6 and
+// 1 - y^2 / 2 to within 2e-12 and 1e-9.
+__device__ __forceinline__ float2 turn_phasor_tab(uint32_t p, const float2* tab) {
+  const uint32_t k = (p + 0x800000u) >> 24;
+  const int32_t r = (int32_t)(p << 8) >> 8;             // p - k 2^24, in [-2^23, 2^23)
+  const float y = (float)r * 1.46291807926715968e-9f;   // 2 pi / 2^32
+  const float y2 = y * y;
+  const float s = fmaf(y2 * y, -1.66666667e-1f, y);
+  const float c = fmaf(y2, -0.5f, 1.0f);
+  const float2 t = tab[k];
+  return make_float2(fmaf(t.x, c, -t.y * s), fmaf(t.y, c, t.x * s));
+}
+__device__ __forceinline__ void seed_phasor_tab(uint4 e, uint32_t f0, const float2* tab, float2* w, float2* step) {
+  const PhaseInc inc = {e.y, e.x};
+  *w = turn_phasor_tab(phase_at(inc, f0), tab);
+  *step = make_float2(__uint_as_float(e.z), __uint_as_float(e.w));
 }
 
 // Row of register r of a 32x32 accumulator in a lane of half h (= lane / 32).
@@ -158,6 +187,7 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
   constexpr int PW = FB * NT * 32 * RW;      // words per plane
   __shared__ uint4 zs[2 * 2 * PW / 4];       // two stage buffers, each a head plane then a tail plane
   __shared__ float colscale[2 * NT + 2];     // power-of-two scales of the group's chunks
+  __shared__ float2 sctab[256];              // phasors of k / 256 turn
 
   const WTile tl = facw_tile(n_bb, n_rt, n_g);
   if (!tl.ok) return;                        // uniform per workgroup, before any barrier
@@ -166,35 +196,53 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
   const ColGroup g = facw_group<NT>(a, tl, tid);
   const uint32_t f0 = (uint32_t)(tl.bb * FB);
   if (tid < 2 * NT + 2) colscale[tid] = tid < g.nks ? chunk_scale(a.l1max[g.kfirst + tid]) : 1.0f;
+  {
+    float sn, cs;
+    sincos_turn((uint32_t)tid << 24, &sn, &cs);
+    sctab[tid] = make_float2(cs, sn);
+  }
 
   // staging data of a stage, in registers: X of (channel cb + cl, chunk kb + i kstep), bins
-  // f0, f0 + 1, and the fine-table entry of (channel, sb)
+  // f0, f0 + 1, and the fine-table entry of (channel, sb).  Each register is loaded again, for
+  // the stage after next, as soon as it has been used, so that every load has a whole stage to
+  // arrive (the stage barrier does not wait for global loads).
   float4 xr[NT];
   uint4 vr;
   // The stage's window of X (channels cb .. cb + 15) and of the fine table through buffer
   // descriptors: channels past n_chan read as zero, and so stage zeros (columns past B N read
   // other finite data, whose products land in output columns that are not stored).
-  auto fetch = [&](int cb) {
+  auto x_rsrc = [&](int cb) {
     const int nc = min(kWKc, a.n_chan - cb);
-    const __amdgpu_buffer_rsrc_t rx = raw_rsrc(a.X + (int64_t)cb * g.N * a.pitch, (int64_t)nc * g.N * a.pitch * 8);
+    return raw_rsrc(a.X + (int64_t)cb * g.N * a.pitch, (int64_t)nc * g.N * a.pitch * 8);
+  };
+  auto fetch_x = [&](__amdgpu_buffer_rsrc_t rx, int i) {
+    // 24-bit products: rows < 2^24, 8 pitch < 2^24 for L <= 2^16
+    xr[i] = load_f4(rx, __umul24((uint32_t)(g.cl * g.N + g.kb + i * g.kstep), (uint32_t)a.pitch * 8u) + f0 * 8u);
+  };
+  auto fetch_v = [&](int cb) {
+    const int nc = min(kWKc, a.n_chan - cb);
     const __amdgpu_buffer_rsrc_t rv = raw_rsrc(a.vtab + (int64_t)cb * g.B, (int64_t)nc * g.B * 16);
     vr = load_u4(rv, (uint32_t)(g.cl * g.B + g.sb) * 16u);
+  };
+  auto fetch = [&](int cb) {
+    fetch_v(cb);
+    const __amdgpu_buffer_rsrc_t rx = x_rsrc(cb);
 #pragma unroll
-    for (int i = 0; i < NT; ++i)   // 24-bit products: rows < 2^24, 8 pitch < 2^24 for L <= 2^16
-      xr[i] = load_f4(rx, __umul24((uint32_t)(g.cl * g.N + g.kb + i * g.kstep), (uint32_t)a.pitch * 8u) + f0 * 8u);
+    for (int i = 0; i < NT; ++i) fetch_x(rx, i);
   };
   // Z of tile i (both bins), scaled, split and stored in the two column layouts
   float2 v0, v1;
   auto seed_v = [&]() {
     float2 vs;
-    seed_phasor(vr, f0, &v0, &vs);
+    seed_phasor_tab(vr, f0, sctab, &v0, &vs);
     v1 = cmul(v0, vs);
   };
   auto deposit = [&](uint32_t* zw, int i) {
-    const float sk = colscale[min(g.kb + i * g.kstep - g.kfirst, 2 * NT + 1)];
+    const float sk = BF ? 1.0f : colscale[min(g.kb + i * g.kstep - g.kfirst, 2 * NT + 1)];
 #pragma unroll
     for (int f = 0; f < FB; ++f) {
-      const float2 x = f ? make_float2(xr[i].z * sk, xr[i].w * sk) : make_float2(xr[i].x * sk, xr[i].y * sk);
+      float2 x = f ? make_float2(xr[i].z, xr[i].w) : make_float2(xr[i].x, xr[i].y);
+      if constexpr (!BF) x = make_float2(x.x * sk, x.y * sk);   // BF16 has the range of FP32
       const float2 z = cmul(f ? v1 : v0, x);
       uint32_t zh, zl;
       split_pair<BF>(z.x, z.y, &zh, &zl);
@@ -228,6 +276,50 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
 
   uint32_t* const zbase = reinterpret_cast<uint32_t*>(zs);
   const int n_st = (a.n_chan + kWKc - 1) / kWKc;
+  V8 bh[2][NT], bl[2][NT];
+  auto ldblk = [&](const uint32_t* zr, int blk, int r) {
+    const int s = blk / FB, f = blk % FB;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      const int wo = ((f * NT + i) * 32 + (lane & 31)) * RW + 8 * s + 4 * h;
+      bh[r][i] = __builtin_bit_cast(V8, *(const uint4*)(zr + wo));
+      bl[r][i] = __builtin_bit_cast(V8, *(const uint4*)(zr + PW + wo));
+    }
+  };
+  // coarse phasors: w / sp of K-step 0 (channels cb + 4 h + u), wn / spn of K-step 1
+  float2 w[4], sp[4], wn[4], spn[4];
+  V8 Ahi, Alo, Nhi, Nlo;                     // A operands of this block and of the next one
+  auto split_next = [&](float2* wv, const float2* spv) {
+    uint32_t ah[4], al[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      split_pair<BF>(wv[u].x, wv[u].y, &ah[u], &al[u]);
+      wv[u] = cmul(wv[u], spv[u]);           // the next bin
+    }
+    Nhi = __builtin_bit_cast(V8, make_uint4(ah[0], ah[1], ah[2], ah[3]));
+    Nlo = __builtin_bit_cast(V8, make_uint4(al[0], al[1], al[2], al[3]));
+  };
+  auto products = [&](int f, int r) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[f][i] = H::mfma(Ahi, bh[r][i], acc[f][i]);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[f][i] = H::mfma(Ahi, bl[r][i], acc[f][i]);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[f][i] = H::mfma(Alo, bh[r][i], acc[f][i]);
+  };
+  // Interleave of a block: every product followed by vector work, the next block's B operand
+  // reads spread over the first 2 NT products.  The fence after it keeps each block's share of
+  // the vector work (seeds, splits, staging) where the code puts it.
+  auto interleave = [&](bool reads) {
+#pragma unroll
+    for (int i = 0; i < 3 * NT; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, kWValuPerMfma, 0);
+      if (reads && i < 2 * NT) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
   __syncthreads();                           // colscale
   fetch(0);
   fetch_u(0, 0);
@@ -236,79 +328,92 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
 #pragma unroll
   for (int i = 0; i < NT; ++i) deposit(zbase, i);
   fetch(kWKc);
-  // Per stage, the products run block by block, a block (K-step s, bin f) being NT tiles that
-  // share the A operands: the hi.hi products of all NT tiles, then their hi.lo, then their lo.hi,
-  // so that NT - 1 other products separate two updates of one accumulator (back to back, each
-  // would wait for the previous one and hold up the vector work between them).  The B operands
-  // of the next block are read from LDS while a block's products run, its A operands are split
-  // before it, the phasors of K-step 1 are seeded during K-step 0, and the next stage's staging
-  // is spread over the blocks.  The body has no branch, so all of it is one scheduling region.
+#pragma unroll
+  for (int u = 0; u < 4; ++u) seed_phasor_tab(tn[u], f0, sctab, &w[u], &sp[u]);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) seed_phasor_tab(tn[4 + u], f0, sctab, &wn[u], &spn[u]);
+  split_next(w, sp);
+  Ahi = Nhi;
+  Alo = Nlo;
+  seed_v();
+  fetch_v(2 * kWKc);
+  fetch_u(kWKc, 0);
+  // Per stage of 16 channels, four blocks (K-step s, bin f) of 3 NT products on the A operands
+  // (coarse phasors, split) of one K-step and bin.  Software pipeline: each block splits the
+  // next block's A operands, reads its B operands from LDS, and does a quarter of the seeding
+  // and staging work of the next stage:
+  //   block 0: seeds of K-step 1 (channels 2, 3 of the half), staging of tiles 0, 1
+  //   block 1: seeds of the next stage's K-step 0 (channels 0, 1), tiles 2, 3
+  //   block 2: the same for channels 2, 3, tiles 4, 5
+  //   block 3: seeds of the next stage's K-step 1 (channels 0, 1), tile 6, the next V
+  // Coarse-table entries are loaded right after their last use, two blocks or more ahead.
   for (int st = 0; st < n_st; ++st) {
-    __syncthreads();                         // stage st staged; the other buffer no longer read
+    lds_barrier();                           // stage st staged; the other buffer no longer read
     const uint32_t* zr = zbase + (st & 1) * 2 * PW;
     uint32_t* zw = zbase + ((st + 1) & 1) * 2 * PW;
     const int cb = st * kWKc;
-    seed_v();                                // V of the next stage (unused after the last)
-    V8 bh[2][NT], bl[2][NT];
-    auto ldblk = [&](int blk, int r) {
-      const int s = blk / FB, f = blk % FB;
+    const __amdgpu_buffer_rsrc_t rxn = x_rsrc(cb + 2 * kWKc);
+    ldblk(zr, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    // block 0: K-step 0, bin f0
 #pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const int wo = ((f * NT + i) * 32 + (lane & 31)) * RW + 8 * s + 4 * h;
-        bh[r][i] = __builtin_bit_cast(V8, *(const uint4*)(zr + wo));
-        bl[r][i] = __builtin_bit_cast(V8, *(const uint4*)(zr + PW + wo));
-      }
-    };
-    ldblk(0, 0);
-    pin_lds_reads();
-    float2 w[4], sp[4], wn[4], spn[4];
+    for (int u = 2; u < 4; ++u) seed_phasor_tab(tn[4 + u], f0, sctab, &wn[u], &spn[u]);
+    split_next(w, sp);                       // K-step 0, bin f0 + 1
+    ldblk(zr, 1, 1);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) seed_phasor(tn[u], f0, &w[u], &sp[u]);
-    fetch_u(cb + kWKc, 0);                   // channels past n_chan are clamped
-    V8 Ahi, Alo;
-    auto split_a = [&]() {
-      uint32_t ah[4], al[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        split_pair<BF>(w[u].x, w[u].y, &ah[u], &al[u]);
-        w[u] = cmul(w[u], sp[u]);            // the next bin
-      }
-      Ahi = __builtin_bit_cast(V8, make_uint4(ah[0], ah[1], ah[2], ah[3]));
-      Alo = __builtin_bit_cast(V8, make_uint4(al[0], al[1], al[2], al[3]));
-    };
-    split_a();
-#pragma unroll
-    for (int blk = 0; blk < 2 * FB; ++blk) {
-      const int f = blk % FB, r = blk & 1;
-      if (blk > 0) {
-        if (blk == FB) {                     // K-step 1 begins
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            w[u] = wn[u];
-            sp[u] = spn[u];
-          }
-          fetch_u(cb + kWKc, 1);
-        }
-        split_a();
-      }
-      if (blk == 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) seed_phasor(tn[4 + u], f0, &wn[u], &spn[u]);
-      }
-      if (blk + 1 < 2 * FB) ldblk(blk + 1, r ^ 1);
-      pin_lds_reads();
-#pragma unroll
-      for (int i = 0; i < NT; ++i) { acc[f][i] = H::mfma(Ahi, bh[r][i], acc[f][i]); }
-      pin_lds_reads();
-      if (blk * 2 < NT) deposit(zw, blk * 2);
-#pragma unroll
-      for (int i = 0; i < NT; ++i) { acc[f][i] = H::mfma(Ahi, bl[r][i], acc[f][i]); }
-      pin_lds_reads();
-      if (blk * 2 + 1 < NT) deposit(zw, blk * 2 + 1);
-#pragma unroll
-      for (int i = 0; i < NT; ++i) { acc[f][i] = H::mfma(Alo, bh[r][i], acc[f][i]); }
+    for (int i = 0; i < 2 && i < NT; ++i) {
+      deposit(zw, i);
+      fetch_x(rxn, i);
     }
-    fetch((st + 2) * kWKc);
+    fetch_u(cb + kWKc, 1);                   // K-step 1 entries of the next stage (blocks 3 and 0)
+    products(0, 0);
+    interleave(true);
+    Ahi = Nhi;
+    Alo = Nlo;
+    // block 1: K-step 0, bin f0 + 1
+    split_next(wn, spn);                     // K-step 1, bin f0
+#pragma unroll
+    for (int u = 0; u < 2; ++u) seed_phasor_tab(tn[u], f0, sctab, &w[u], &sp[u]);
+    ldblk(zr, 2, 0);
+#pragma unroll
+    for (int i = 2; i < 4 && i < NT; ++i) {
+      deposit(zw, i);
+      fetch_x(rxn, i);
+    }
+    products(1, 1);
+    interleave(true);
+    Ahi = Nhi;
+    Alo = Nlo;
+    // block 2: K-step 1, bin f0
+    split_next(wn, spn);                     // K-step 1, bin f0 + 1
+#pragma unroll
+    for (int u = 2; u < 4; ++u) seed_phasor_tab(tn[u], f0, sctab, &w[u], &sp[u]);
+    fetch_u(cb + 2 * kWKc, 0);               // K-step 0 entries of the stage after next
+    ldblk(zr, 3, 1);
+#pragma unroll
+    for (int i = 4; i < 6 && i < NT; ++i) {
+      deposit(zw, i);
+      fetch_x(rxn, i);
+    }
+    products(0, 0);
+    interleave(true);
+    Ahi = Nhi;
+    Alo = Nlo;
+    // block 3: K-step 1, bin f0 + 1
+    split_next(w, sp);                       // the next stage's K-step 0, bin f0
+#pragma unroll
+    for (int u = 0; u < 2; ++u) seed_phasor_tab(tn[4 + u], f0, sctab, &wn[u], &spn[u]);
+#pragma unroll
+    for (int i = 6; i < NT; ++i) {
+      deposit(zw, i);
+      fetch_x(rxn, i);
+    }
+    seed_v();                                // V of the stage after next, for the next deposits
+    fetch_v(cb + 3 * kWKc);
+    products(1, 1);
+    interleave(false);
+    Ahi = Nhi;
+    Alo = Nlo;
   }
 
   // Epilogue: lane (column j < 16 of tile i) holds Re of column q = q0 + 16 i + j for the rows
@@ -324,7 +429,7 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
     const int q = g.q0 + 16 * i + (jj & 15);
     const int k = q >> g.lgB;
     const int b = q & (g.B - 1);
-    const float inv = 1.0f / colscale[min(k - g.kfirst, 2 * NT + 1)];
+    const float inv = BF ? 1.0f : 1.0f / colscale[min(k - g.kfirst, 2 * NT + 1)];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       float2 y[FB];
@@ -538,6 +643,7 @@ FacwChoice facw_choose(int n_dm, int n_chunks) {
   // 128-row group over all bins): the 7-tile shape is the fastest per tile as well as per
   // column, the others lose more than their share of matrix work.
   constexpr double kTileCost[kFacwNtMax - kFacwNtMin + 1] = {18.0, 24.0, 30.0, 15.0};
+  constexpr double kFacwMinEff = 0.7;
   FacwChoice best;
   double best_cost = 0.0;
   for (int fine : {16, 8}) {
@@ -548,6 +654,9 @@ FacwChoice facw_choose(int n_dm, int n_chunks) {
       // useful (trial, chunk) pairs over the padded tile area (coarse rows x columns)
       const double eff = (double)n_dm * n_chunks / ((double)rt * kWRows * (double)grp * 16 * nt);
       const double cost = (double)rt * (double)grp * kTileCost[nt - kFacwNtMin];
+      // shapes that pad more than 30 % of the tile area are not taken (the planner then keeps
+      // the direct kernels when no shape is left)
+      if (eff < kFacwMinEff) continue;
       if (best.fine == 0 || cost < best_cost) {
         best.fine = fine;
         best.coarse = coarse;
