@@ -24,6 +24,26 @@ struct PhaseInc {
   uint32_t lo;  // next 32 bits
 };
 
+// Raw buffer loads: a wave-uniform base and byte count (a descriptor in scalar registers) and
+// a per-lane 32-bit byte offset.  Offsets at or past the byte count read as zero, so a kernel
+// can stage zeros for channels past the last one without branches or 64-bit address
+// arithmetic.  The byte count saturates at 2^31 - 1: a window must be smaller than 2 GiB.
+constexpr int kRawBufferWord3 = 0x00020000;   // descriptor word 3: untyped 32-bit data, no swizzle
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int64_t bytes) {
+  const int n = bytes <= 0 ? 0 : (bytes >= 0x7fffffff ? 0x7fffffff : (int)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRawBufferWord3);
+}
+__device__ __forceinline__ float4 load_f4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const f4v v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ uint4 load_u4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const u4v v = __builtin_bit_cast(u4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
 // Top 32 bits of (inc * f) mod 2^64, for f < 2^32.
 __device__ __forceinline__ uint32_t phase_at(PhaseInc inc, uint32_t f) {
   return inc.hi * f + __umulhi(inc.lo, f);
@@ -60,6 +80,32 @@ __device__ __forceinline__ void seed_phasor(uint4 e, uint32_t f0, float2* w, flo
   sincos_turn(phase_at(inc, f0), &s, &c);
   *w = make_float2(c, s);
   *step = make_float2(__uint_as_float(e.z), __uint_as_float(e.w));
+}
+
+// sin and cos of 2 pi p / 2^32 from a 256-entry table of the phasors of k / 256 turn (nearest k)
+// and the rotation by the remainder |y| <= pi / 256, whose sine and cosine are y - y^3 / 6 and
+// 1 - y^2 / 2 to within 2e-12 and 1e-9.
+__device__ __forceinline__ float2 turn_phasor_tab(uint32_t p, const float2* tab) {
+  const uint32_t k = (p + 0x800000u) >> 24;
+  const int32_t r = (int32_t)(p << 8) >> 8;             // p - k 2^24, in [-2^23, 2^23)
+  const float y = (float)r * 1.46291807926715968e-9f;   // 2 pi / 2^32
+  const float y2 = y * y;
+  const float s = fmaf(y2 * y, -1.66666667e-1f, y);
+  const float c = fmaf(y2, -0.5f, 1.0f);
+  const float2 t = tab[k];
+  return make_float2(fmaf(t.x, c, -t.y * s), fmaf(t.y, c, t.x * s));
+}
+// seed_phasor with the table form of sincos_turn.
+__device__ __forceinline__ void seed_phasor_tab(uint4 e, uint32_t f0, const float2* tab, float2* w, float2* step) {
+  const PhaseInc inc = {e.y, e.x};
+  *w = turn_phasor_tab(phase_at(inc, f0), tab);
+  *step = make_float2(__uint_as_float(e.z), __uint_as_float(e.w));
+}
+// Entry k of that table (k < 256), from sincos_turn.
+__device__ __forceinline__ float2 turn_table_entry(uint32_t k) {
+  float s, c;
+  sincos_turn(k << 24, &s, &c);
+  return make_float2(c, s);
 }
 
 // The same from a per-channel linear entry {inc0.lo, inc0.hi, d.lo, d.hi} for trial j: the

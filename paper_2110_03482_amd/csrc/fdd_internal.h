@@ -241,6 +241,7 @@ hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st);
 hipError_t launch_split_x(float2* X, const unsigned int* l1max, int n_chan, int n_chunks, int64_t pitch, bool bf16,
                           hipStream_t st);
 bool phasor_mfma_f32_supported(int n_chunks);
+bool phasor_mfma_f32_window_ok(int64_t x_chunks, int64_t pitch);
 bool phasor_split_supported(int n_chunks);
 
 // Chunk tiling of the direct matrix-core kernels, which hold at most kDirectMaxChunks chunks

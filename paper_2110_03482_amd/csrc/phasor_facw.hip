@@ -106,46 +106,8 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// sin and cos of 2 pi p / 2^32 from a 256-entry table of the phasors of k / 256 turn (nearest k)
-// and the rotation by the remainder |y| <= pi / 256, whose sine and cosine are y - y^3 / 6 and
-// 1 - y^2 / 2 to within 2e-12 and 1e-9.
-__device__ __forceinline__ float2 turn_phasor_tab(uint32_t p, const float2* tab) {
-  const uint32_t k = (p + 0x800000u) >> 24;
-  const int32_t r = (int32_t)(p << 8) >> 8;             // p - k 2^24, in [-2^23, 2^23)
-  const float y = (float)r * 1.46291807926715968e-9f;   // 2 pi / 2^32
-  const float y2 = y * y;
-  const float s = fmaf(y2 * y, -1.66666667e-1f, y);
-  const float c = fmaf(y2, -0.5f, 1.0f);
-  const float2 t = tab[k];
-  return make_float2(fmaf(t.x, c, -t.y * s), fmaf(t.y, c, t.x * s));
-}
-__device__ __forceinline__ void seed_phasor_tab(uint4 e, uint32_t f0, const float2* tab, float2* w, float2* step) {
-  const PhaseInc inc = {e.y, e.x};
-  *w = turn_phasor_tab(phase_at(inc, f0), tab);
-  *step = make_float2(__uint_as_float(e.z), __uint_as_float(e.w));
-}
-
 // Row of register r of a 32x32 accumulator in a lane of half h (= lane / 32).
 __device__ __forceinline__ int acc_row(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
-
-// Raw buffer loads: a wave-uniform base and byte count (a descriptor in scalar registers) and
-// a per-lane 32-bit byte offset.  Offsets at or past the byte count read as zero, which is how
-// channels past the last one stage zeros, without branches or 64-bit address arithmetic.
-constexpr int kRawBufferWord3 = 0x00020000;   // descriptor word 3: untyped 32-bit data, no swizzle
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, int64_t bytes) {
-  const int n = bytes <= 0 ? 0 : (bytes >= 0x7fffffff ? 0x7fffffff : (int)bytes);
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, kRawBufferWord3);
-}
-__device__ __forceinline__ float4 load_f4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  const f4v v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
-  return make_float4(v[0], v[1], v[2], v[3]);
-}
-__device__ __forceinline__ uint4 load_u4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  const u4v v = __builtin_bit_cast(u4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
-  return make_uint4(v[0], v[1], v[2], v[3]);
-}
 
 // Column-group geometry shared by both precisions.
 struct ColGroup {
@@ -196,11 +158,7 @@ __global__ __launch_bounds__(256, 1) void k_phasor_facw_split(PhasorArgs a, int 
   const ColGroup g = facw_group<NT>(a, tl, tid);
   const uint32_t f0 = (uint32_t)(tl.bb * FB);
   if (tid < 2 * NT + 2) colscale[tid] = tid < g.nks ? chunk_scale(a.l1max[g.kfirst + tid]) : 1.0f;
-  {
-    float sn, cs;
-    sincos_turn((uint32_t)tid << 24, &sn, &cs);
-    sctab[tid] = make_float2(cs, sn);
-  }
+  sctab[tid] = turn_table_entry((uint32_t)tid);
 
   // staging data of a stage, in registers: X of (channel cb + cl, chunk kb + i kstep), bins
   // f0, f0 + 1, and the fine-table entry of (channel, sb).  Each register is loaded again, for

@@ -57,6 +57,10 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
   constexpr int PER = (KC * 8 * NT * (FB / 2) + 255) / 256;
   __shared__ float bre2[2][PLANE];
   __shared__ float bim2[2][PLANE];
+  // sin/cos table of the seeds, where its 2 KiB leave the workgroups per CU unchanged
+  constexpr int kLdsBase = 4 * PLANE * (int)sizeof(float);
+  constexpr bool TAB = !LIN && (163840 / (kLdsBase + 2048) == 163840 / kLdsBase);
+  __shared__ float2 sctab[TAB ? 256 : 1];
 
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
@@ -76,6 +80,7 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
     bre2[0][i] = bre2[1][i] = 0.0f;
     bim2[0][i] = bim2[1][i] = 0.0f;
   }
+  if constexpr (TAB) sctab[tid] = turn_table_entry((uint32_t)tid);
 
   // Staging map, fixed for all channel blocks: element e = tid + 256 j is the float4 of bins
   // (2 fp, 2 fp + 1) of chunk k of channel cl of the block.  The chunk varies fastest, so the
@@ -92,14 +97,20 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
     loff[j] = cl * CST + 2 * fp * NCOL + k;
     ccl[j] = e < nel ? cl : KC;                                 // KC marks "no element"
   }
+  // Each group's X rows are read through a buffer descriptor over the rows of its KC channels
+  // (channels past n_chan read as zeros), so an element's byte offset is the same in every
+  // group; an element slot that holds nothing points past any window.  The window stays below
+  // 2 GiB (KC XC pitch 8 bytes; checked by the planner).
+  uint32_t xoff[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j)
+    xoff[j] = ccl[j] < KC ? (uint32_t)(((int64_t)ccl[j] * XC * a.pitch + goff[j]) * 8) : 0xFFFFFFF0u;
   float4 pf[PER];
   auto fetch = [&](int cb) {
+    const int nc = min(KC, a.n_chan - cb);
+    const __amdgpu_buffer_rsrc_t rx = raw_rsrc(a.X + (int64_t)cb * XC * a.pitch, (int64_t)nc * XC * a.pitch * 8);
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      pf[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (ccl[j] < KC && cb + ccl[j] < a.n_chan)
-        pf[j] = *(const float4*)(a.X + (int64_t)(cb + ccl[j]) * XC * a.pitch + goff[j]);
-    }
+    for (int j = 0; j < PER; ++j) pf[j] = load_f4(rx, xoff[j]);
   };
   auto deposit = [&](float* bre, float* bim) {
 #pragma unroll
@@ -136,39 +147,38 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
       for (int nt = 0; nt < NT; ++nt) acc[m][f][nt] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 
   fetch(0);
-  __syncthreads();                            // padding zeroed
+  __syncthreads();                            // padding zeroed, table filled
   deposit(bre2[0], bim2[0]);
   __syncthreads();
   int it = 0;
-  // phase-table entries of the lane's (DM, channel) seeds, loaded one group ahead (with LIN
-  // the channel's linear entry, the same for every DM)
-  auto entry = [&](int c, int m) -> uint4 {
-    if constexpr (LIN) return a.ltab[c];
-    else return a.ptab[(int64_t)c * a.n_dm + dmi[m]];
+  // Phase-table entries of the lane's (DM, channel) seeds (with LIN the channel's linear entry,
+  // the same for every DM), through a descriptor over the group's KC channels like X: byte
+  // offsets the same in every group, channels past n_chan read as zero entries (phasor 1, step
+  // 0, against staged zeros).  Each entry is loaded for the next group as soon as its seed and
+  // steps are formed, into the registers it leaves.
+  uint32_t toff[KC / 4][MW];
+#pragma unroll
+  for (int s = 0; s < KC / 4; ++s)
+#pragma unroll
+    for (int m = 0; m < MW; ++m)
+      toff[s][m] = LIN ? (uint32_t)((4 * s + cq) * 16) : (uint32_t)(((4 * s + cq) * a.n_dm + dmi[m]) * 16);
+  auto tab_rsrc = [&](int cb) {
+    const int nc = min(KC, a.n_chan - cb);
+    if constexpr (LIN) return raw_rsrc(a.ltab + cb, (int64_t)nc * 16);
+    else return raw_rsrc(a.ptab + (int64_t)cb * a.n_dm, (int64_t)nc * a.n_dm * 16);
   };
   uint4 tn[KC / 4][MW];
+  {
+    const __amdgpu_buffer_rsrc_t rt = tab_rsrc(0);
 #pragma unroll
-  for (int s = 0; s < KC / 4; ++s) {
-    int c = 4 * s + cq;
-    if (c >= a.n_chan) c = a.n_chan - 1;
+    for (int s = 0; s < KC / 4; ++s)
 #pragma unroll
-    for (int m = 0; m < MW; ++m) tn[s][m] = entry(c, m);
+      for (int m = 0; m < MW; ++m) tn[s][m] = load_u4(rt, toff[s][m]);
   }
   for (int cb = 0; cb < a.n_chan; cb += KC, ++it) {
     const float* bre = bre2[it & 1];
     const float* bim = bim2[it & 1];
-    uint4 tc[KC / 4][MW];
-#pragma unroll
-    for (int s = 0; s < KC / 4; ++s)
-#pragma unroll
-      for (int m = 0; m < MW; ++m) tc[s][m] = tn[s][m];
-#pragma unroll
-    for (int s = 0; s < KC / 4; ++s) {
-      int c = cb + KC + 4 * s + cq;
-      if (c >= a.n_chan) c = a.n_chan - 1;
-#pragma unroll
-      for (int m = 0; m < MW; ++m) tn[s][m] = entry(c, m);
-    }
+    const __amdgpu_buffer_rsrc_t rtn = tab_rsrc(cb + KC);
     if (cb + KC < a.n_chan) fetch(cb + KC);   // in flight while this block computes
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
@@ -178,8 +188,9 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
 #pragma unroll
       for (int m = 0; m < MW; ++m) {
         float2 w, step;
-        if constexpr (LIN) seed_phasor_linear(tc[s][m], (uint32_t)(dmi[m] + a.lin_j0), (uint32_t)fb0, &w, &step);
-        else seed_phasor(tc[s][m], (uint32_t)fb0, &w, &step);
+        if constexpr (LIN) seed_phasor_linear(tn[s][m], (uint32_t)(dmi[m] + a.lin_j0), (uint32_t)fb0, &w, &step);
+        else if constexpr (TAB) seed_phasor_tab(tn[s][m], (uint32_t)fb0, sctab, &w, &step);
+        else seed_phasor(tn[s][m], (uint32_t)fb0, &w, &step);
         float wr[FB], wi[FB];
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
@@ -187,6 +198,7 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
           wi[f] = w.y;
           w = cmul(w, step);
         }
+        tn[s][m] = load_u4(rtn, toff[s][m]);
 #pragma unroll
         for (int f = 0; f < FB; ++f)
 #pragma unroll
@@ -284,6 +296,10 @@ int persistent_blocks(const void* kernel, int threads, int64_t cap) {
 
 bool phasor_mfma_f32_supported(int n_chunks) { return n_chunks >= 3 && n_chunks <= 24; }
 
+// The kernels read X through descriptors over the rows of 8 or 16 channels (x_chunks rows of
+// pitch complex bins each), whose byte count must stay below 2^31.
+bool phasor_mfma_f32_window_ok(int64_t x_chunks, int64_t pitch) { return 16 * 8 * x_chunks * pitch <= 0x7fffffff; }
+
 namespace {
 template <int FB, int KC, int MW, bool LIN>
 hipError_t launch_tile_lin(const PhasorArgs& a, hipStream_t st) {
@@ -310,7 +326,9 @@ hipError_t launch_tile(const PhasorArgs& a, hipStream_t st) {
 
 // Tile variants (tuning): bins per workgroup x channels per LDS stage x DM sub-tiles per wave.
 hipError_t launch_phasor_mfma_f32(const PhasorArgs& a, hipStream_t st) {
-  if (!phasor_mfma_f32_supported(a.n_chunks)) return hipErrorInvalidValue;
+  if (!phasor_mfma_f32_supported(a.n_chunks) ||
+      !phasor_mfma_f32_window_ok(a.x_chunks > 0 ? a.x_chunks : a.n_chunks, a.pitch))
+    return hipErrorInvalidValue;
   switch (a.tile_variant) {
     case 1: return launch_tile<16, 8, 1>(a, st);
     case 2: return launch_tile<8, 16, 1>(a, st);

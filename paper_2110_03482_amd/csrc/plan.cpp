@@ -505,7 +505,8 @@ fdd_status fdd_plan(const fdd_plan_desc* desc, fdd_plan_t* out) {
     return fail(FDD_E_UNSUPPORTED, "grid dimension limit exceeded");
   }
   // direct matrix-core kernels, over chunk groups of at most kDirectMaxChunks when there are more
-  p->kernel = (d.precision == FDD_FP32 && phasor_mfma_f32_supported(chunk_group_max((int)p->n_chunks)))
+  p->kernel = (d.precision == FDD_FP32 && phasor_mfma_f32_supported(chunk_group_max((int)p->n_chunks)) &&
+               phasor_mfma_f32_window_ok(p->n_chunks, p->pitch))
                   ? "mfma_f32" : "valu";
   // tuning override of the matrix-core tile shape
   if (const char* tv = std::getenv("FDD_TILE_VARIANT")) {

@@ -211,6 +211,18 @@ def test_direct_kernels_take_any_chunk_count():
         assert _dry(w, mode="round").kernel == "mfma_f32"
 
 
+def test_direct_fp32_kernel_needs_a_small_descriptor_window():
+    """The FP32 matrix-core kernel reads X through descriptors over the rows of up to 16 channels,
+    which must stay below 2 GiB (16 x chunks x pitch x 8 bytes): a 2^24-sample band at
+    L = 2^16 (329 chunks) fits, a 2^25-sample one (658 chunks) goes to the VALU kernel."""
+    for log_n, kernel in ((24, "mfma_f32"), (25, "valu")):
+        w = W.tiny_random(12, 16, 1 << log_n, 64, 1 << 16, single_chunk=False, input_kind="f32", dm_max=50.0)
+        p = _dry(w)
+        g = p.geometry
+        assert p.kernel == kernel, (log_n, g.n_chunks, p.kernel)
+        assert (16 * 8 * g.n_chunks * g.bins_padded <= 0x7fffffff) == (kernel == "mfma_f32")
+        p.close()
+
 def test_batch_rejects_without_device_calls():
     lib = fdd.library()
     d = fdd.BatchDesc()
