@@ -233,6 +233,7 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
   __shared__ uint4 lhi[PLANEW / 4];
   __shared__ uint4 llo[PLANEW / 4];
   __shared__ float colscale[32];
+  __shared__ float2 sctab[256];           // phasors of k / 256 turn, for the seeds
 
   const TileXY tl = fac_tile(bid, n_at, n_bb);
   if (tl.bb >= n_bb) return;
@@ -250,28 +251,37 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
     llo[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   if (tid < N) colscale[tid] = chunk_scale(a.l1max[tid]);
+  sctab[tid] = turn_table_entry((uint32_t)tid);
   uint32_t* whi = reinterpret_cast<uint32_t*>(lhi);
   uint32_t* wlo = reinterpret_cast<uint32_t*>(llo);
 
   // staging element e = tid + 256 j: channel cl = e % KC (fastest: consecutive LDS words),
-  // column q = e / KC = b N + k
+  // column q = e / KC = b N + k.  X and the fine table are read through descriptors over the
+  // stage's KC channels (channels past n_chan read as zeros), at byte offsets that are the same
+  // in every stage; a slot that holds no element points past any window.
   float4 pf[PER][FB / 2];
   uint4 pv[PER];
+  uint32_t xoff[PER], voff[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + 256 * j;
+    const int cl = e % KC;
+    const int q = e / KC;
+    const int b = q / N;
+    const int k = q - b * N;
+    const bool ok = e < nel;
+    xoff[j] = ok ? (uint32_t)((((int64_t)cl * N + k) * a.pitch + fb0) * 8) : 0xFFFFFFF0u;
+    voff[j] = ok ? (uint32_t)((cl * B + b) * 16) : 0xFFFFFFF0u;
+  }
   auto fetch = [&](int cb) {
+    const int nc = min(KC, a.n_chan - cb);
+    const __amdgpu_buffer_rsrc_t rx = raw_rsrc(a.X + (int64_t)cb * N * a.pitch, (int64_t)nc * N * a.pitch * 8);
+    const __amdgpu_buffer_rsrc_t rv = raw_rsrc(a.vtab + (int64_t)cb * B, (int64_t)nc * B * 16);
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-      const int e = tid + 256 * j;
-      const int cl = e % KC;
-      const int q = e / KC;
-      const int b = q / N;
-      const int k = q - b * N;
-      const int c = cb + cl;
-      const bool ok = e < nel && c < a.n_chan;
-      const float2* src = a.X + ((int64_t)(ok ? c : 0) * N + k) * a.pitch + fb0;
 #pragma unroll
-      for (int i = 0; i < FB / 2; ++i)
-        pf[j][i] = ok ? *(const float4*)(src + 2 * i) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      pv[j] = ok ? a.vtab[(int64_t)c * B + b] : make_uint4(0u, 0u, 0u, 0u);
+      for (int i = 0; i < FB / 2; ++i) pf[j][i] = load_f4(rx, xoff[j] + 16u * i);
+      pv[j] = load_u4(rv, voff[j]);
     }
   };
   auto deposit = [&]() {
@@ -284,7 +294,7 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
       const int k = q - (q / N) * N;
       const float sk = colscale[k];
       float2 v, st;
-      seed_phasor(pv[j], (uint32_t)fb0, &v, &st);
+      seed_phasor_tab(pv[j], (uint32_t)fb0, sctab, &v, &st);
 #pragma unroll
       for (int i = 0; i < FB / 2; ++i) {
 #pragma unroll
@@ -325,13 +335,15 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
     __syncthreads();
     if (cb + KC < a.n_chan) fetch(cb + KC);
 
-    // coarse phasors of this lane's row for channels cb + 4 cq .. + 3
+    // coarse phasors of this lane's row for channels cb + 4 cq .. + 3 (channels past n_chan
+    // read as zero entries, against data staged as zeros)
     float2 w[4], st[4];
+    {
+      const int nc = min(KC, a.n_chan - cb);
+      const __amdgpu_buffer_rsrc_t rp = raw_rsrc(a.ptab + (int64_t)cb * A, (int64_t)nc * A * 16);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int c = cb + 4 * cq + q;
-      if (c >= a.n_chan) c = a.n_chan - 1;          // data staged as zeros
-      seed_phasor(a.ptab[(int64_t)c * A + arow], (uint32_t)fb0, &w[q], &st[q]);
+      for (int q = 0; q < 4; ++q)
+        seed_phasor_tab(load_u4(rp, (uint32_t)(((4 * cq + q) * A + arow) * 16)), (uint32_t)fb0, sctab, &w[q], &st[q]);
     }
     const int rowbase = (lane & 15) * ROWW + 4 * cq;
 #pragma unroll
@@ -429,7 +441,7 @@ __global__ __launch_bounds__(256) void k_phasor_fac_f32(PhasorArgs a, int n_at, 
 }
 
 template <bool BF, int NT, int FB>
-__global__ __launch_bounds__(256, 2) void k_phasor_fac_split(PhasorArgs a, int n_at, int n_bb) {
+__global__ __launch_bounds__(256, 3) void k_phasor_fac_split(PhasorArgs a, int n_at, int n_bb) {
   phasor_fac_split_body<BF, NT, FB>(a, fac_block(), n_at, n_bb, threadIdx.x);
 }
 
