@@ -47,6 +47,7 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
   __shared__ uint4 lhi[PLANEW / 4];
   __shared__ uint4 llo[PLANEW / 4];
   __shared__ float colscale[32];
+  __shared__ float2 sctab[256];          // phasors of k / 256 turn, for the seeds
 
   const int xcd = bid % kXcds;
   const int slot = bid / kXcds;
@@ -66,6 +67,7 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
     llo[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   if (tid < N) colscale[tid] = chunk_scale(a.l1max[tid]);
+  sctab[tid] = turn_table_entry((uint32_t)tid);
   uint32_t* whi = reinterpret_cast<uint32_t*>(lhi);
   uint32_t* wlo = reinterpret_cast<uint32_t*>(llo);
 
@@ -126,13 +128,21 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
   // Phase-table entries of this lane's DM for the 4 channels it seeds, loaded one stage ahead so
   // that their latency is spent while the previous stage computes.  With two column tiles the
   // 16 extra registers would cost a wave of occupancy, so that shape loads them in the stage.
+  // They come through a descriptor over the stage's 16 channels: the byte offsets are the same
+  // in every stage, and channels past n_chan read as zero entries (against data staged as zeros).
   constexpr bool kAhead = NT != 2;
-  uint4 tnext[4];
+  uint32_t toff[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int c = 4 * cq + q;
-    if (c >= a.n_chan) c = a.n_chan - 1;
-    tnext[q] = a.ptab[(int64_t)c * a.n_dm + dm];
+  for (int q = 0; q < 4; ++q) toff[q] = (uint32_t)(((4 * cq + q) * a.n_dm + dm) * 16);
+  auto tab_rsrc = [&](int cb) {
+    const int nc = min(KC, a.n_chan - cb);
+    return raw_rsrc(a.ptab + (int64_t)cb * a.n_dm, (int64_t)nc * a.n_dm * 16);
+  };
+  uint4 tnext[4];
+  {
+    const __amdgpu_buffer_rsrc_t rt = tab_rsrc(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tnext[q] = load_u4(rt, toff[q]);
   }
   __syncthreads();                               // colscale
   fetch(0);
@@ -144,22 +154,16 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
     // phasors of this lane's DM for channels cb + 4 cq .. + 3 (clamped channels: data staged as zeros)
     float2 w[4], st[4];
     if constexpr (!kAhead) {
+      const __amdgpu_buffer_rsrc_t rt = tab_rsrc(cb);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int c = cb + 4 * cq + q;
-        if (c >= a.n_chan) c = a.n_chan - 1;
-        tnext[q] = a.ptab[(int64_t)c * a.n_dm + dm];
-      }
+      for (int q = 0; q < 4; ++q) tnext[q] = load_u4(rt, toff[q]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) seed_phasor(tnext[q], (uint32_t)fb0, &w[q], &st[q]);
+    for (int q = 0; q < 4; ++q) seed_phasor_tab(tnext[q], (uint32_t)fb0, sctab, &w[q], &st[q]);
     if constexpr (kAhead) {
+      const __amdgpu_buffer_rsrc_t rt = tab_rsrc(cb + KC);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int c = cb + KC + 4 * cq + q;
-        if (c >= a.n_chan) c = a.n_chan - 1;
-        tnext[q] = a.ptab[(int64_t)c * a.n_dm + dm];
-      }
+      for (int q = 0; q < 4; ++q) tnext[q] = load_u4(rt, toff[q]);
     }
     if (cb + KC < a.n_chan) fetch(cb + KC);      // in flight while this stage computes
     const int rowbase = (lane & 15) * ROWW + 4 * cq;     // words
