@@ -596,11 +596,11 @@ hipError_t launch_facw_nt(const PhasorArgs& a, int precision, hipStream_t st) {
 }  // namespace
 
 FacwChoice facw_choose(int n_dm, int n_chunks) {
-  // Time per workgroup tile by column-tile count nt = 4, 5, 6, 7, relative, measured with the
-  // FP16 split kernel on the paper-shaped bin and channel counts (18, 24, 30 and 15 ms per
-  // 128-row group over all bins): the 7-tile shape is the fastest per tile as well as per
-  // column, the others lose more than their share of matrix work.
-  constexpr double kTileCost[kFacwNtMax - kFacwNtMin + 1] = {18.0, 24.0, 30.0, 15.0};
+  // Time per workgroup tile by column-tile count nt = 4, 5, 6, 7, measured with the FP16 split
+  // kernel on the paper-shaped bin and channel counts (ms per column group of 128 coarse rows
+  // over all bins): the 7-tile shape is the fastest per tile (1.8 ms against 2.9-3.7), the
+  // 4-tile one the cheapest per group.
+  constexpr double kTileCost[kFacwNtMax - kFacwNtMin + 1] = {11.4, 15.7, 21.9, 12.7};
   constexpr double kFacwMinEff = 0.7;
   FacwChoice best;
   double best_cost = 0.0;
