@@ -212,17 +212,20 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
       }
     }
     if constexpr (FB == 8 && MW == 1) {
-      // Scheduling only: keep two B-operand reads (ds_read2, two MFMAs each) in flight ahead of
-      // the matrix instructions; left alone, the scheduler waits for each read right before
-      // its two MFMAs.  The other tile shapes lose occupancy to the extra registers.
+      // Scheduling only: issue four B-operand reads (ds_read2, two MFMAs each) before the first
+      // matrix instruction and one more after every two, so that three are in flight while a
+      // pair of products waits for the oldest; left alone, the scheduler waits for each read
+      // right before its two MFMAs.  (Two, five or six ahead measured slower; eight makes the
+      // register allocator fall back to one.)  The other tile shapes lose occupancy to the
+      // extra registers.
       constexpr int kReads = (KC / 4) * FB * NT;
-      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);      // DS reads
+      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);      // DS reads
 #pragma unroll
-      for (int i = 0; i < kReads - 2; ++i) {
+      for (int i = 0; i < kReads - 4; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);    // MFMA
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
     }
     // the other buffer was last read in the previous group, which every wave has left
     if (cb + KC < a.n_chan) deposit(bre2[(it + 1) & 1], bim2[(it + 1) & 1]);
