@@ -220,7 +220,9 @@ Class make_class(const fdd_plan_s* p, int N, bool fac, bool fac_default) {
     std::snprintf(key, sizeof key, "fp32/L%lld/n1%s", (long long)p->L, fs);
     c.cands.push_back({kValu, 1, false});
   } else {
-    const bool small = !phasor_mfma_f32_supported(NG);   // the single plan keeps these on the VALU
+    // the single plan keeps these on the VALU (few chunks, or rows too long for the kernels'
+    // 2 GiB descriptor window)
+    const bool small = !phasor_mfma_f32_supported(NG) || !phasor_mfma_f32_window_ok(N, p->pitch);
     std::snprintf(key, sizeof key, "fp32/L%lld/%s%d%s", (long long)p->L, small ? "n" : "nt", small ? N : c.nt, fs);
     if (small) c.cands.push_back({kValu, 4, false});
     else
