@@ -303,7 +303,7 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
                              : make_float2(pf[j][i].x * sk, pf[j][i].y * sk);
           const float2 z = cmul(v, x);
           uint32_t zh, zl;
-          split_pair<BF, false>(z.x, z.y, &zh, &zl);
+          split_pair<BF>(z.x, z.y, &zh, &zl);
           const int f = 2 * i + h;
           const int w0 = f * BINW + q * ROWW + cl;          // column q: (Re, -Im)
           const int w1 = f * BINW + (q + BN) * ROWW + cl;   // column q + B N: (Im, Re)
@@ -351,7 +351,7 @@ __device__ __forceinline__ void phasor_fac_split_body(const PhasorArgs& a, const
       uint32_t ah[4], al[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        split_pair<BF, false>(w[q].x, w[q].y, &ah[q], &al[q]);
+        split_pair<BF>(w[q].x, w[q].y, &ah[q], &al[q]);
         w[q] = cmul(w[q], st[q]);
       }
       const V8 Ahi = __builtin_bit_cast(V8, make_uint4(ah[0], ah[1], ah[2], ah[3]));

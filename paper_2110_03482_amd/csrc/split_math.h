@@ -52,7 +52,8 @@ __device__ __forceinline__ float opaque_one() {
 // Head/tail split of a pair (x, y): hi = (half(x), half(y)), lo = (half(x - hi_x), half(y - hi_y)).
 // The residuals x - hi_x are exact in float32 (hi_x holds the leading 11 or 8 bits of x).  MIX
 // (float16): the residuals through v_fma_mix_f32; the same values, fewer instructions, though in
-// some kernels more live registers (the factorised power-spectrum kernel loses a wave).
+// some kernels more live registers (the single-chunk factorised kernel keeps it inside its
+// register budget only with a launch bound of three waves per SIMD).
 template <bool BF, bool MIX = true>
 __device__ __forceinline__ void split_pair(float x, float y, uint32_t* hi, uint32_t* lo) {
   const float2v v = {x, y};
