@@ -57,9 +57,10 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
   constexpr int PER = (KC * 8 * NT * (FB / 2) + 255) / 256;
   __shared__ float bre2[2][PLANE];
   __shared__ float bim2[2][PLANE];
-  // sin/cos table of the seeds, where its 2 KiB leave the workgroups per CU unchanged
+  // sin/cos table of the seeds (and, with LIN, of the step phasors), where its 2 KiB leave the
+  // workgroups per CU unchanged
   constexpr int kLdsBase = 4 * PLANE * (int)sizeof(float);
-  constexpr bool TAB = !LIN && (163840 / (kLdsBase + 2048) == 163840 / kLdsBase);
+  constexpr bool TAB = (163840 / (kLdsBase + 2048) == 163840 / kLdsBase);
   __shared__ float2 sctab[TAB ? 256 : 1];
 
   const int xcd = bid % kXcds;
@@ -188,7 +189,13 @@ __device__ __forceinline__ void phasor_mfma_f32_body(const PhasorArgs& a, const 
 #pragma unroll
       for (int m = 0; m < MW; ++m) {
         float2 w, step;
-        if constexpr (LIN) seed_phasor_linear(tn[s][m], (uint32_t)(dmi[m] + a.lin_j0), (uint32_t)fb0, &w, &step);
+        if constexpr (LIN && TAB) {            // seed_phasor_linear with table sin/cos
+          const uint4 e = tn[s][m];
+          const uint64_t inc = (((uint64_t)e.y << 32) | e.x) + (uint64_t)(uint32_t)(dmi[m] + a.lin_j0) * (((uint64_t)e.w << 32) | e.z);
+          const PhaseInc pinc = {(uint32_t)(inc >> 32), (uint32_t)inc};
+          w = turn_phasor_tab(phase_at(pinc, (uint32_t)fb0), sctab);
+          step = turn_phasor_tab(pinc.hi, sctab);
+        } else if constexpr (LIN) seed_phasor_linear(tn[s][m], (uint32_t)(dmi[m] + a.lin_j0), (uint32_t)fb0, &w, &step);
         else if constexpr (TAB) seed_phasor_tab(tn[s][m], (uint32_t)fb0, sctab, &w, &step);
         else seed_phasor(tn[s][m], (uint32_t)fb0, &w, &step);
         float wr[FB], wi[FB];
