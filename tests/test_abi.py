@@ -223,6 +223,21 @@ def test_direct_fp32_kernel_needs_a_small_descriptor_window():
         assert (16 * 8 * g.n_chunks * g.bins_padded <= 0x7fffffff) == (kernel == "mfma_f32")
         p.close()
 
+def test_facw_gpu_cases_cover_the_tile_counts_in_use():
+    """The factorised GPU parity cases (tests/test_gpu_facw.py) must reach every column-group width
+    the planner picks for them: 4, 5 and 7 tiles of 32 columns (6 is never the cheapest)."""
+    import dataclasses
+    import test_gpu_facw as F
+    seen = set()
+    for seed, n_chan, n_samp, n_dm, L, kind, dm_hi in F.CASES:
+        w = W.tiny_random(seed, n_chan, n_samp, n_dm, L, single_chunk=False, input_kind=kind)
+        w = dataclasses.replace(w, dms=np.linspace(0.0, dm_hi, n_dm))
+        p = _dry(w, mode="exact", precision="fp16_split")
+        assert p.kernel == "facw_f16_split", (seed, p.kernel)
+        seen.add(p.factors[2])
+        p.close()
+    assert {4, 5, 7} <= seen, seen
+
 def test_batch_rejects_without_device_calls():
     lib = fdd.library()
     d = fdd.BatchDesc()

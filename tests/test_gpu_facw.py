@@ -74,6 +74,8 @@ CASES = [
     (15, 16, 50000, 2048, 4096, "u8", 60.0),          # 16 channels (one stage), L = 4096
     (16, 32, 59000, 2048, 2048, "u8", 40.0),          # 42 chunks (above the direct kernels' 24)
     (17, 24, 90000, 2048, 2048, "f32", 40.0),         # 64 chunks
+    (18, 40, 5500, 2048, 2048, "f32", 40.0),          # 4 chunks: one group of 4 tiles
+    (19, 24, 9000, 1024, 2048, "u8", 25.0),           # 6 chunks, 8 fine trials: 4 tiles, ragged 8-bit tail
 ]
 
 
