@@ -30,7 +30,9 @@ constexpr int kXcds = 8;
 
 // PRE: X already holds, per complex value, the split words {hi, lo} of the scaled (Re, Im)
 // pair (k_split_x), so the staging only rearranges them.
-template <bool BF, int NT, int FB, bool PRE = false>
+// DESC: X through a descriptor over the stage's 16 channels (32-bit offsets; the window, 16 x
+// x_chunks x pitch x 8 bytes, must stay below 2 GiB).
+template <bool BF, int NT, int FB, bool PRE = false, bool DESC = false>
 __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int bid, const int n_dmt,
                                                   const int n_bb,
     const int tid) {
@@ -75,15 +77,31 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
   // (2 fp, 2 fp + 1) of (cb + cl, k); prefetched one stage ahead into registers.
   float4 pf[PER];
   auto fetch = [&](int cb) {
+    if constexpr (DESC) {
+      // channels past n_chan read as zeros; a slot that holds no element points past the window
+      const int nc = min(KC, a.n_chan - cb);
+      const __amdgpu_buffer_rsrc_t rx = raw_rsrc(a.X + (int64_t)cb * XC * a.pitch, (int64_t)nc * XC * a.pitch * 8);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
-      const int cl = e % KC;
-      const int fp = (e / KC) % (FB / 2);
-      const int k = e / (KC * (FB / 2));
-      const int c = cb + cl;
-      pf[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (e < nel && c < a.n_chan) pf[q] = *(const float4*)(a.X + ((int64_t)c * XC + k) * a.pitch + fb0 + 2 * fp);
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        const int cl = e % KC;
+        const int fp = (e / KC) % (FB / 2);
+        const int k = e / (KC * (FB / 2));
+        const uint32_t off = e < nel ? ((uint32_t)(cl * XC + k) * (uint32_t)a.pitch + (uint32_t)(fb0 + 2 * fp)) * 8u
+                                     : 0xFFFFFFF0u;
+        pf[q] = load_f4(rx, off);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        const int cl = e % KC;
+        const int fp = (e / KC) % (FB / 2);
+        const int k = e / (KC * (FB / 2));
+        const int c = cb + cl;
+        pf[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (e < nel && c < a.n_chan) pf[q] = *(const float4*)(a.X + ((int64_t)c * XC + k) * a.pitch + fb0 + 2 * fp);
+      }
     }
   };
   auto deposit = [&]() {
@@ -232,9 +250,9 @@ __device__ __forceinline__ void phasor_split_body(const PhasorArgs& a, const int
 // linear workgroup id; grids are 2-D only to keep each dimension below 2^32 work-items
 __device__ __forceinline__ int linear_block_s() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
-template <bool BF, int NT, int FB>
+template <bool BF, int NT, int FB, bool DESC>
 __global__ __launch_bounds__(256, 2) void k_phasor_split(PhasorArgs a, int n_dmt, int n_bb) {
-  phasor_split_body<BF, NT, FB, true>(a, linear_block_s(), n_dmt, n_bb, threadIdx.x);
+  phasor_split_body<BF, NT, FB, true, DESC>(a, linear_block_s(), n_dmt, n_bb, threadIdx.x);
 }
 
 // Scale and split X in place, once per call instead of once per DM tile: every complex value
@@ -267,7 +285,7 @@ __global__ __launch_bounds__(256, 2) void k_phasor_split_grouped(Group<PhasorArg
 bool phasor_split_supported(int n_chunks) { return n_chunks >= 1 && n_chunks <= 24; }
 
 namespace {
-template <bool BF, int FB>
+template <bool BF, int FB, bool DESC>
 hipError_t launch_split_fb(const PhasorArgs& a, hipStream_t st) {
   const int n_dmt = (a.n_dm + 63) / 64;
   const int n_bb = (a.n_bins + FB - 1) / FB;
@@ -276,9 +294,9 @@ hipError_t launch_split_fb(const PhasorArgs& a, hipStream_t st) {
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid = linear_grid(blocks), block(256);
   switch ((2 * a.n_chunks + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_phasor_split<BF, 1, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;
-    case 2: hipLaunchKernelGGL((k_phasor_split<BF, 2, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;
-    case 3: hipLaunchKernelGGL((k_phasor_split<BF, 3, FB>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 1: hipLaunchKernelGGL((k_phasor_split<BF, 1, FB, DESC>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 2: hipLaunchKernelGGL((k_phasor_split<BF, 2, FB, DESC>), grid, block, 0, st, a, n_dmt, n_bb); break;
+    case 3: hipLaunchKernelGGL((k_phasor_split<BF, 3, FB, DESC>), grid, block, 0, st, a, n_dmt, n_bb); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -288,7 +306,10 @@ hipError_t launch_split_fb(const PhasorArgs& a, hipStream_t st) {
 hipError_t launch_phasor_split(const PhasorArgs& a, bool bf16, hipStream_t st) {
   if (!phasor_split_supported(a.n_chunks)) return hipErrorInvalidValue;
   if (a.P != nullptr && a.n_chunks != 1) return hipErrorInvalidValue;
-  return bf16 ? launch_split_fb<true, 8>(a, st) : launch_split_fb<false, 8>(a, st);
+  const int64_t xc = a.x_chunks > 0 ? a.x_chunks : a.n_chunks;
+  if (16 * 8 * xc * a.pitch <= 0x7fffffff)
+    return bf16 ? launch_split_fb<true, 8, true>(a, st) : launch_split_fb<false, 8, true>(a, st);
+  return bf16 ? launch_split_fb<true, 8, false>(a, st) : launch_split_fb<false, 8, false>(a, st);
 }
 
 hipError_t launch_split_x(float2* X, const unsigned int* l1max, int n_chan, int n_chunks, int64_t pitch, bool bf16,
